@@ -1,0 +1,434 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of them re-runs the oracle's own
+formula: they use algebraic identities of the paper, closed forms, brute force
+on tiny lattices, dense linear algebra, and symmetries.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import gamma, mobius, overlap, redblack, wilson
+from paper_1501_04950_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).reshape(-1)) / max(np.linalg.norm(b.reshape(-1)), 1e-300)
+
+
+def cdot(a, b):
+    return np.vdot(a.reshape(-1), b.reshape(-1))
+
+
+# ---------------------------------------------------------------- conventions
+def test_gamma_algebra():
+    """Clifford algebra {g_mu, g_nu} = 2 delta, Hermiticity, gamma5 and P+- of eq.(coeff)."""
+    g = gamma.GAMMA
+    for a in range(4):
+        assert np.allclose(g[a], g[a].conj().T)
+        for b in range(4):
+            assert np.allclose(g[a] @ g[b] + g[b] @ g[a], 2.0 * (a == b) * np.eye(4))
+        assert np.allclose(gamma.GAMMA5 @ g[a] + g[a] @ gamma.GAMMA5, 0)
+    assert np.allclose(gamma.GAMMA5 @ gamma.GAMMA5, np.eye(4))
+    assert np.allclose(gamma.GAMMA5, np.diag([1, 1, -1, -1]))  # chiral basis: P+ = spins 0,1
+    pp, pm = gamma.P_PLUS, gamma.P_MINUS
+    assert np.allclose(pp + pm, np.eye(4)) and np.allclose(pp @ pp, pp)
+    assert np.allclose(pm @ pm, pm) and np.allclose(pp @ pm, 0)
+
+
+def test_su3_inputs():
+    dims = (4, 4, 2, 2)
+    u = synth.su3_field(dims, 0.5, 7)
+    us = synth.ape_smear(u, dims, 0.5, 2)
+    for f in (u, us):
+        eye = np.einsum("...ba,...bc->...ac", f.conj(), f)
+        assert np.allclose(eye, np.eye(3), atol=1e-13)
+        assert np.allclose(np.linalg.det(f), 1.0, atol=1e-13)
+    assert abs(synth.plaquette(synth.unit_field(dims), dims) - 1.0) < 1e-15
+    assert synth.plaquette(us, dims) > synth.plaquette(u, dims)  # smearing smooths
+
+
+# ---------------------------------------------------------------- D_w, eq.(wilson)
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (2, 2, 2, 2), (2, 4, 6, 4)])
+def test_dw_gamma5_hermiticity(dims):
+    """D_w^dag = gamma5 D_w gamma5 for eq.(wilson): <phi, D_w psi> = <g5 D_w g5 phi, psi>."""
+    U = synth.su3_field(dims, 0.6, 11)
+    psi, phi = synth.gaussian_source(dims, 1), synth.gaussian_source(dims, 2)
+    g5 = lambda f: gamma.spin_apply(gamma.GAMMA5, f)
+    lhs = cdot(phi, wilson.dw(U, psi, -1.8, dims))
+    rhs = cdot(g5(wilson.dw(U, g5(phi), -1.8, dims)), psi)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("apbc", [True, False])
+def test_dw_dag_is_adjoint(apbc):
+    dims = (4, 2, 4, 6)
+    U = synth.su3_field(dims, 0.6, 12)
+    psi, phi = synth.gaussian_source(dims, 3), synth.gaussian_source(dims, 4)
+    lhs = cdot(phi, wilson.dw(U, psi, 0.3, dims, apbc))
+    rhs = cdot(wilson.dw_dag(U, phi, 0.3, dims, apbc), psi)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def _coords(dims):
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx),
+                             indexing="ij")
+    return [a.reshape(-1) for a in (x, y, z, t)]
+
+
+@pytest.mark.parametrize("apbc", [False, True])
+def test_dw_free_plane_wave(apbc):
+    """U = 1: D_w exp(ip.x) u = exp(ip.x) [(4+M5) - sum cos p + i sum gamma sin p] u."""
+    dims = (4, 6, 4, 8)
+    rng = np.random.default_rng(5)
+    n = [1, 2, 3, 1]
+    p = [2 * np.pi * n[k] / dims[k] for k in range(3)]
+    p.append((2 * n[3] + (1 if apbc else 0)) * np.pi / dims[3])
+    x = _coords(dims)
+    phase = np.exp(1j * sum(p[k] * x[k] for k in range(4)))
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    psi = phase[:, None, None] * u[None]
+    out = wilson.dw(synth.unit_field(dims), psi, -1.8, dims, apbc)
+    expect = phase[:, None, None] * (overlap.free_dw(p, -1.8) @ u)[None]
+    assert rel(out, expect) < 1e-13
+
+
+def test_dw_gauge_covariance():
+    """D(U^Omega) Omega psi = Omega D(U) psi, U^Omega_mu(x) = Omega(x) U_mu(x) Omega(x+mu)^dag."""
+    dims = (4, 4, 2, 6)
+    vol = synth.volume(dims)
+    U = synth.su3_field(dims, 0.7, 13)
+    om = synth.random_su3(vol, 2.0, np.random.Generator(np.random.PCG64(99)))
+    x = _coords(dims)
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        xs = [c.copy() for c in x]
+        xs[mu] = (xs[mu] + 1) % dims[mu]
+        nb = xs[0] + dims[0] * (xs[1] + dims[1] * (xs[2] + dims[2] * xs[3]))
+        Ug[mu] = om @ U[mu] @ np.conj(np.swapaxes(om[nb], -1, -2))
+    psi = synth.gaussian_source(dims, 6)
+    rot = lambda f: np.einsum("xab,xsb->xsa", om, f)
+    assert rel(wilson.dw(Ug, rot(psi), -1.8, dims), rot(wilson.dw(U, psi, -1.8, dims))) < 1e-13
+
+
+def test_dw_bruteforce_elements():
+    """Every matrix element of eq.(wilson), written with explicit coordinates and
+    explicit boundary signs, on a lattice with extent-2 directions (where x+mu
+    and x-mu coincide and both hops add)."""
+    dims = (2, 2, 2, 4)
+    M5 = -1.4
+    vol = synth.volume(dims)
+    U = synth.su3_field(dims, 0.8, 14)
+    x = _coords(dims)
+    n = 12 * vol
+    ref = np.zeros((n, n), dtype=np.complex128)
+    one = np.eye(4)
+    for s in range(vol):
+        for a in range(12):
+            ref[12 * s + a, 12 * s + a] += 4.0 + M5
+        for mu in range(4):
+            c = [x[k][s] for k in range(4)]
+            fwd, bwd = list(c), list(c)
+            fwd[mu] = (c[mu] + 1) % dims[mu]
+            bwd[mu] = (c[mu] - 1) % dims[mu]
+            sf = -1.0 if (mu == 3 and c[3] == dims[3] - 1) else 1.0
+            sb = -1.0 if (mu == 3 and c[3] == 0) else 1.0
+            jf = fwd[0] + dims[0] * (fwd[1] + dims[1] * (fwd[2] + dims[2] * fwd[3]))
+            jb = bwd[0] + dims[0] * (bwd[1] + dims[1] * (bwd[2] + dims[2] * bwd[3]))
+            blk_f = -0.5 * sf * np.kron(one - gamma.GAMMA[mu], U[mu][s])
+            blk_b = -0.5 * sb * np.kron(one + gamma.GAMMA[mu], U[mu][jb].conj().T)
+            ref[12 * s:12 * s + 12, 12 * jf:12 * jf + 12] += blk_f
+            ref[12 * s:12 * s + 12, 12 * jb:12 * jb + 12] += blk_b
+    dense = overlap.dense_matrix(lambda f: wilson.dw(U, f, M5, dims), (vol, 4, 3))
+    assert np.abs(dense - ref).max() < 1e-14
+
+
+# ---------------------------------------------------------------- D_alpha, eq.(mobius1)
+def _rand_params(Ls, seed, alpha, m=0.1, dims=(2, 2, 2, 2)):
+    rng = np.random.default_rng(seed)
+    b = rng.uniform(1.0, 2.0, Ls)
+    c = rng.uniform(0.2, 0.9, Ls)
+    return redblack.Params.make(dims, Ls, -1.7, m, alpha, b, c)
+
+
+@pytest.mark.parametrize("Ls", [2, 3, 6])
+def test_alpha_one_is_conventional_moebius(Ls):
+    """Sec. 1/abstract: D_alpha and the conventional operator agree for alpha = 1."""
+    dims = (4, 2, 2, 4)
+    p = _rand_params(Ls, 20 + Ls, 1.0, dims=dims)
+    U = synth.su3_field(dims, 0.5, 21)
+    psi = synth.gaussian_field5(dims, Ls, 22)
+    a = mobius.apply_D(U, psi, p.M5, p.m, 1.0, p.b, p.c, dims)
+    b = mobius.apply_D_conventional(U, psi, p.M5, p.m, p.b, p.c, dims)
+    assert rel(a, b) < 1e-14
+
+
+def _G(psi, alpha):
+    """G = diag(P- + alpha P+, alpha, ..., alpha, P+ + alpha P-)."""
+    out = alpha * psi.copy()
+    pp, pm = gamma.P_PLUS, gamma.P_MINUS
+    out[0] = gamma.spin_apply(pm + alpha * pp, psi[0])
+    out[-1] = gamma.spin_apply(pp + alpha * pm, psi[-1])
+    return out
+
+
+@pytest.mark.parametrize("Ls", [2, 3, 6])
+def test_alpha_column_rotation(Ls):
+    """Sec. 2: D_alpha P = D_1 P A with A = diag(1, alpha, ..., alpha); and the
+    equivalent right scaling D_alpha = D_1 G that the GPU path builds on."""
+    dims = (2, 4, 2, 2)
+    alpha = 0.63
+    p = _rand_params(Ls, 30 + Ls, alpha, dims=dims)
+    U = synth.su3_field(dims, 0.5, 31)
+    v = synth.gaussian_field5(dims, Ls, 32)
+    D = lambda f, al: mobius.apply_D(U, f, p.M5, p.m, al, p.b, p.c, dims)
+    lhs = D(mobius.apply_P(v), alpha)
+    rhs = D(mobius.apply_P(mobius.apply_A(v, alpha)), 1.0)
+    assert rel(lhs, rhs) < 1e-14
+    assert rel(D(v, alpha), D(_G(v, alpha), 1.0)) < 1e-14
+
+
+@pytest.mark.parametrize("Ls", [2, 4, 5])
+def test_DP_transfer_form(Ls):
+    """Sec. 2: D_alpha P = gamma5 [[Q_1- c_-, a Q_1+, ...], [0, a Q_2-, a Q_2+, ...], ...,
+    [Q_Ls+ c_+, 0, ..., a Q_Ls-]] with Q_i+- = gamma5 D_w (b_i P+- + c_i P-+) +- 1 and
+    c_+- = P+- - m P-+ (App. A definitions).  This pins every block of eq.(mobius1),
+    including the -m corners, against an independent form printed in the paper."""
+    dims = (2, 2, 4, 2)
+    alpha, m = 0.77, 0.13
+    p = _rand_params(Ls, 40 + Ls, alpha, m=m, dims=dims)
+    U = synth.su3_field(dims, 0.5, 41)
+    v = synth.gaussian_field5(dims, Ls, 42)
+    g5 = lambda f: gamma.spin_apply(gamma.GAMMA5, f)
+    pp, pm = gamma.P_PLUS, gamma.P_MINUS
+    dwf = lambda f: wilson.dw(U, f, p.M5, dims)
+
+    def Q(i, sign, f):
+        r = (p.b[i] * pp + p.c[i] * pm) if sign > 0 else (p.b[i] * pm + p.c[i] * pp)
+        return g5(dwf(gamma.spin_apply(r, f))) + sign * f
+
+    c_plus, c_minus = pp - m * pm, pm - m * pp
+    expect = np.zeros_like(v)
+    expect[0] = Q(0, -1, gamma.spin_apply(c_minus, v[0])) + alpha * Q(0, +1, v[1])
+    for i in range(1, Ls - 1):
+        expect[i] = alpha * Q(i, -1, v[i]) + alpha * Q(i, +1, v[i + 1])
+    L = Ls - 1
+    expect[L] = Q(L, +1, gamma.spin_apply(c_plus, v[0])) + alpha * Q(L, -1, v[L])
+    expect = g5(expect)
+    got = mobius.apply_D(U, mobius.apply_P(v), p.M5, m, alpha, p.b, p.c, dims)
+    assert rel(got, expect) < 1e-14
+
+
+def test_D_dag_is_adjoint():
+    dims = (2, 2, 2, 4)
+    p = _rand_params(5, 50, 0.7, dims=dims)
+    U = synth.su3_field(dims, 0.5, 51)
+    u, v = synth.gaussian_field5(dims, 5, 52), synth.gaussian_field5(dims, 5, 53)
+    lhs = cdot(u, mobius.apply_D(U, v, p.M5, p.m, p.alpha, p.b, p.c, dims))
+    rhs = cdot(mobius.apply_D_dag(U, u, p.M5, p.m, p.alpha, p.b, p.c, dims), v)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_P_inverse():
+    v = synth.gaussian_field5((2, 2, 2, 2), 5, 54)
+    assert rel(mobius.apply_P_inv(mobius.apply_P(v)), v) < 1e-15
+    assert rel(mobius.apply_P(mobius.apply_P_inv(v)), v) < 1e-15
+
+
+# ---------------------------------------------------------------- eq.(redblack)
+def _dense_on(apply_fn, mask_sites, Ls, vol):
+    """Dense matrix of apply_fn restricted to the sites where mask_sites is True."""
+    sites = np.nonzero(mask_sites)[0]
+    n = Ls * len(sites) * 12
+    cols = []
+    for k in range(n):
+        s, rest = divmod(k, len(sites) * 12)
+        j, a = divmod(rest, 12)
+        e = np.zeros((Ls, vol, 4, 3), dtype=np.complex128)
+        e[s, sites[j], a // 3, a % 3] = 1.0
+        cols.append(apply_fn(e)[:, sites].reshape(-1))
+    return np.stack(cols, axis=1)
+
+
+def test_schur_complement_solves_full_system():
+    """eq.(redblack) with the prep and reconstruction of the Schur complement
+    gives the solution of the full 5D system D_alpha psi = rho (dense LU)."""
+    dims, Ls = (2, 2, 2, 2), 4
+    vol = synth.volume(dims)
+    p = _rand_params(Ls, 60, 0.8, dims=dims)
+    U = synth.su3_field(dims, 0.5, 61)
+    rb = redblack.RedBlack(U, p)
+    full = overlap.dense_matrix(rb.D, (Ls, vol, 4, 3))
+    rho = synth.gaussian_field5(dims, Ls, 62)
+    psi = np.linalg.solve(full, rho.reshape(-1)).reshape(rho.shape)
+    black = redblack.parity(dims) == 0
+    dbb = _dense_on(rb.Dbb, black, Ls, vol)
+    phi = rb.schur_rhs(rho)
+    xb = np.linalg.solve(dbb, phi[:, black].reshape(-1)).reshape(Ls, -1, 4, 3)
+    psi_b = np.zeros_like(rho)
+    psi_b[:, black] = xb
+    psi_rb = psi_b + rb.reconstruct_red(psi_b, rho)
+    assert rel(psi_rb, psi) < 1e-12
+
+
+def test_Dbb_dag_is_adjoint():
+    dims, Ls = (4, 2, 2, 4), 5
+    p = _rand_params(Ls, 70, 0.6, dims=dims)
+    U = synth.su3_field(dims, 0.6, 71)
+    rb = redblack.RedBlack(U, p)
+    u = synth.gaussian_field5(dims, Ls, 72) * rb.black
+    v = synth.gaussian_field5(dims, Ls, 73) * rb.black
+    lhs = cdot(u, rb.Dbb(v))
+    rhs = cdot(rb.Dbb_dag(u), v)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_Dbb_alpha_similarity_and_spectrum():
+    """D_alpha = D_1 G makes D_bb(alpha) = G^-1 D_bb(1) G, so the spectrum of
+    D_bb does not depend on alpha; check the similarity on vectors and the
+    similarity invariants tr(D_bb^k) of the dense matrices."""
+    dims, Ls = (2, 2, 2, 2), 4
+    vol = synth.volume(dims)
+    U = synth.su3_field(dims, 0.6, 81)
+    base = _rand_params(Ls, 80, 1.0, dims=dims)
+    rb1 = redblack.RedBlack(U, base)
+    black = redblack.parity(dims) == 0
+    d1 = _dense_on(rb1.Dbb, black, Ls, vol)
+    tr1 = [np.trace(np.linalg.matrix_power(d1, k)) for k in (1, 2, 3)]
+    x = synth.gaussian_field5(dims, Ls, 82) * rb1.black
+    for alpha in (0.5, 1.3):
+        rba = redblack.RedBlack(U, base.with_(alpha=alpha))
+        # G^-1 has the entry 1/alpha wherever G has alpha
+        assert rel(rba.Dbb(x), _G(rb1.Dbb(_G(x, alpha)), 1.0 / alpha)) < 1e-13
+        da = _dense_on(rba.Dbb, black, Ls, vol)
+        tra = [np.trace(np.linalg.matrix_power(da, k)) for k in (1, 2, 3)]
+        for a, b in zip(tra, tr1):
+            assert abs(a - b) <= 1e-11 * abs(b)
+
+
+# ---------------------------------------------------------------- the propagator
+def test_source_lives_on_the_walls():
+    """rho = D_1(1) P b with b = (eta, 0, ...) is non-zero only on the first and last
+    slice: rho_1 = D_w(b_1 P- - c_1 P+) eta + eta, rho_Ls = D_w(b_Ls P+ - c_Ls P-) eta + eta."""
+    dims, Ls = (2, 2, 2, 4), 5
+    p = _rand_params(Ls, 90, 0.7, dims=dims)
+    U = synth.su3_field(dims, 0.5, 91)
+    eta = synth.gaussian_source(dims, 92)
+    rho = redblack.source_rhs(U, eta, p)
+    pp, pm = gamma.P_PLUS, gamma.P_MINUS
+    dwf = lambda f: wilson.dw(U, f, p.M5, dims)
+    r0 = dwf(gamma.spin_apply(p.b[0] * pm - p.c[0] * pp, eta)) + eta
+    rl = dwf(gamma.spin_apply(p.b[-1] * pp - p.c[-1] * pm, eta)) + eta
+    assert rel(rho[0], r0) < 1e-14 and rel(rho[-1], rl) < 1e-14
+    assert np.abs(rho[1:-1]).max() == 0.0
+
+
+def test_y1_matches_transfer_matrix_overlap():
+    """App. A/B: y_1 = D_OV(m)^-1 eta, with D_OV built densely from
+    S = S_1 ... S_Ls, S_i = -Q_i-^-1 Q_i+, for per-slice b_i, c_i and alpha != 1.
+
+    The product of transfer matrices spans many decades when some eigenvalue of
+    the Moebius kernel approaches 1, which would make a dense check meaningless
+    in FP64; the parameters keep cond(S) near 1e5 so the identity is checked to
+    rounding.  The reversed product S_Ls ... S_1 must fail: the check sees the
+    order of the slices."""
+    dims, Ls = (2, 2, 2, 2), 4
+    vol = synth.volume(dims)
+    U = synth.su3_field(dims, 0.5, 101)
+    rng = np.random.default_rng(100)
+    b, c = rng.uniform(0.15, 0.3, Ls), rng.uniform(0.0, 0.1, Ls)
+    p = redblack.Params.make(dims, Ls, 1.0, 0.1, 0.7, b, c)
+    eta = synth.gaussian_source(dims, 102)
+    Dw = overlap.dense_matrix(lambda f: wilson.dw(U, f, p.M5, dims), (vol, 4, 3))
+    dov = overlap.overlap_D4(Dw, vol, p.m, p.b, p.c)
+    rb = redblack.RedBlack(U, p)
+    rho = redblack.source_rhs(U, eta, p)
+    dense = overlap.dense_matrix(rb.D, (Ls, vol, 4, 3))
+    psi = np.linalg.solve(dense, rho.reshape(-1)).reshape(rho.shape)
+    y_lu = redblack.extract_y1(psi)
+    assert rel(dov @ y_lu.reshape(-1), eta.reshape(-1)) < 1e-13
+    dov_rev = overlap.overlap_D4(Dw, vol, p.m, p.b[::-1], p.c[::-1])
+    assert rel(dov_rev @ y_lu.reshape(-1), eta.reshape(-1)) > 1e-4
+    y1, info = redblack.propagator(U, eta, p, tol=1e-13)
+    assert info.converged
+    assert rel(dov @ y1.reshape(-1), eta.reshape(-1)) < 1e-11
+
+
+def test_y1_independent_of_alpha():
+    """eq.(tosolve1): z_1 = y_1 for every alpha."""
+    dims, Ls = (2, 2, 4, 4), 4
+    U = synth.su3_field(dims, 0.5, 111)
+    eta = synth.gaussian_source(dims, 112)
+    base = redblack.Params.make(dims, Ls, -1.8, 0.05, 1.0, 1.5, 0.5)
+    ref, _ = redblack.propagator(U, eta, base, tol=1e-13)
+    for alpha in (0.5, 0.8, 1.2):
+        y, info = redblack.propagator(U, eta, base.with_(alpha=alpha), tol=1e-13)
+        assert info.converged
+        assert rel(y, ref) < 1e-10
+
+
+def test_mass_one_gives_identity():
+    """At m = 1 the overlap operator of eq.(startprop) is the identity, so y_1 = eta."""
+    dims, Ls = (2, 2, 4, 2), 4
+    U = synth.su3_field(dims, 0.5, 121)
+    eta = synth.gaussian_source(dims, 122)
+    p = redblack.Params.make(dims, Ls, -1.8, 1.0, 0.7, 1.5, 0.5)
+    y, info = redblack.propagator(U, eta, p, tol=1e-13)
+    assert rel(y, eta) < 1e-11
+
+
+def test_free_field_momentum_closed_form():
+    """U = 1, antiperiodic t: y_1 for a plane-wave source equals the polar form
+    D_OV(p)^-1 of eq.(polar)/(argument) applied to the spinor."""
+    dims, Ls = (4, 4, 2, 4), 6
+    p_ = redblack.Params.make(dims, Ls, -1.8, 0.1, 0.8, 1.5, 0.5)
+    mom = [2 * np.pi * 1 / 4, 0.0, np.pi, 3 * np.pi / 4]
+    x = _coords(dims)
+    phase = np.exp(1j * sum(mom[k] * x[k] for k in range(4)))
+    rng = np.random.default_rng(131)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    eta = phase[:, None, None] * u[None]
+    y, info = redblack.propagator(synth.unit_field(dims), eta, p_, tol=1e-13)
+    dov = overlap.overlap_tanh_spin(overlap.free_dw(mom, p_.M5), p_.m, 1.5, 0.5, Ls)
+    expect = phase[:, None, None] * np.linalg.solve(dov, u)[None]
+    assert rel(y, expect) < 1e-10
+
+
+def test_free_field_zero_momentum_golden():
+    """Hand-derived D_OV(0) (tests/golden/free_field_p0.json) for a constant source."""
+    g = json.load(open(os.path.join(HERE, "golden", "free_field_p0.json")))
+    pr = g["params"]
+    dims = (2, 2, 2, 4)
+    ratio = g["g_numerator"] / g["g_denominator"]
+    dov0 = 0.5 * ((1 + pr["m"]) + (1 - pr["m"]) * ratio)
+    p = redblack.Params.make(dims, pr["Ls"], pr["M5"], pr["m"], 0.9, pr["b"], pr["c"],
+                             antiperiodic_t=False)
+    eta = np.zeros((synth.volume(dims), 4, 3), dtype=np.complex128)
+    eta[:, 1, 2] = 1.0 - 0.5j
+    eta[:, 2, 0] = 0.25
+    y, info = redblack.propagator(synth.unit_field(dims), eta, p, tol=1e-13)
+    assert rel(y, eta / dov0) < 1e-10
+
+
+def test_redblack_matches_unpreconditioned_and_dense():
+    """The red-black CGLS route gives the same 5D solution as CGLS on the full
+    D_alpha and as a dense LU solve."""
+    dims, Ls = (2, 2, 2, 4), 4
+    vol = synth.volume(dims)
+    U = synth.su3_field(dims, 0.5, 141)
+    p = redblack.Params.make(dims, Ls, -1.8, 0.1, 0.7, 1.5, 0.5)
+    eta = synth.gaussian_source(dims, 142)
+    y, info, psi = redblack.propagator(U, eta, p, tol=1e-13, return_psi=True)
+    rho = redblack.source_rhs(U, eta, p)
+    psi_full, info2 = redblack.solve_unpreconditioned(U, rho, p, tol=1e-13)
+    rb = redblack.RedBlack(U, p)
+    dense = overlap.dense_matrix(rb.D, (Ls, vol, 4, 3))
+    psi_lu = np.linalg.solve(dense, rho.reshape(-1)).reshape(rho.shape)
+    assert rel(psi, psi_lu) < 1e-10
+    assert rel(psi_full, psi_lu) < 1e-10
