@@ -1,0 +1,179 @@
+/*
+ * dwa.h -- C-ABI of libdwa, the MI355X (gfx950) library for the alpha-Moebius
+ * domain-wall operator of H. Neff, "A better conditioned Domain Wall Operator".
+ *
+ * The library applies the red-black operator D_bb = 1 - I_bb^-1 D_br I_rr^-1 D_rb
+ * of D_alpha(m) (Sec. 3, eq.(redblack); D_alpha(m) is the block matrix of Sec. 2,
+ * eq.(mobius1), with D_w the Wilson operator of eq.(wilson)) and its adjoint,
+ * solves D_bb psi_b = phi' with CG on the normal equations (Sec. 3), and returns
+ * the alpha-independent 4D propagator y_1 of D_1(m) P y = D_1(1) P b
+ * (Sec. 2, eq.(tosolve1); App. B, eq.(tosolve)).
+ *
+ * Conventions (fixed here because the paper leaves them open):
+ *   - lattice extents dims = {Lx, Ly, Lz, Lt}; every extent must be even and >= 2
+ *     (the red-black split needs a bipartite lattice);
+ *     4D sites are lexicographic, site = x + Lx*(y + Ly*(z + Lz*t));
+ *   - mu = 0,1,2,3 is x,y,z,t; U_mu(x) sits on the link x -> x+mu and multiplies
+ *     psi(x+mu); the backward hop uses U_mu(x-mu)^dagger;
+ *   - chiral gamma basis, gamma5 = diag(1,1,-1,-1): P+ acts on spins 0,1, P- on 2,3;
+ *   - fermion fields are periodic in x,y,z and antiperiodic in t when
+ *     params.antiperiodic_t is non-zero (a factor -1 on hops across t = Lt-1 <-> 0);
+ *   - slices s = 0..Ls-1 stand for the paper's i_5 = 1..Ls; b[s], c[s] belong to the
+ *     row (output slice) of eq.(mobius1);
+ *   - "black" is the even parity (x+y+z+t even), the parity the CG runs on.
+ *
+ * Layouts:
+ *   canonical links    complex128 [4][V][3][3]        (mu, site, row, column)
+ *   canonical 4D field complex128 [V][4][3]           (site, spin, colour)
+ *   canonical 5D field complex128 [Ls][V][4][3]
+ *   half-lattice field ("SoA") of one parity, precision prec:
+ *                      [Ls][12][Vh] complex, component = spin*3 + colour,
+ *                      Vh = V/2, checkerboard index cb = site/2;
+ *                      F64: 16 B per complex, F32: 8 B, BF16: 4 B (bf16 re, bf16 im).
+ * Complex numbers are interleaved (re, im).
+ *
+ * Memory ownership: every field pointer is a device pointer owned by the caller,
+ * on the device that was current when the context was created.  The library never
+ * frees caller memory.  The context owns its workspace (packed links, s-matrices,
+ * solver vectors, reduction buffers); it allocates in dwa_create / dwa_set_links
+ * and frees in dwa_destroy.  Operator calls do not allocate.
+ *
+ * Streams: all work is enqueued on the stream given to dwa_create (0 = default
+ * stream).  Operator calls return without synchronising; solves synchronise on
+ * their convergence checks and before returning.
+ *
+ * Errors: every call returns a dwa_status; nothing is thrown across the ABI.
+ * Argument validation happens before any HIP call and returns DWA_EINVAL.
+ * dwa_strerror() maps a status to text; dwa_last_error() gives the last detail
+ * message of the calling thread.
+ */
+#ifndef DWA_H
+#define DWA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dwa_ctx dwa_ctx;
+
+typedef enum {
+  DWA_OK = 0,
+  DWA_EINVAL = -1,      /* invalid argument (bad extent, Ls < 2, alpha = 0, null pointer, ...) */
+  DWA_ENOMEM = -2,      /* device allocation failed */
+  DWA_EHIP = -3,        /* a HIP runtime call failed (including "no device") */
+  DWA_ENOCONV = -4,     /* solver reached maxiter; the best iterate and stats are returned */
+  DWA_EBREAKDOWN = -5,  /* CG breakdown: |D_bb p|^2 or |D_bb^dag r|^2 is zero or not finite */
+  DWA_ENAN = -6,        /* non-finite value in an input field */
+  DWA_ESTATE = -7       /* call out of order (e.g. no links set yet) */
+} dwa_status;
+
+typedef enum { DWA_F64 = 0, DWA_F32 = 1, DWA_BF16 = 2 } dwa_prec;
+
+/* Physical parameters of D_alpha(m) (Sec. 2): Wilson mass M5 enters the diagonal
+ * (4 + M5) of eq.(wilson) as written; m is the quark mass; alpha the new parameter;
+ * b, c are host arrays of length Ls (the Moebius coefficients of eq.(coeff)). */
+typedef struct {
+  int dims[4];
+  int Ls;
+  double M5;
+  double m;
+  double alpha;
+  const double *b;
+  const double *c;
+  int antiperiodic_t;
+} dwa_params;
+
+/* Solver options.
+ *   tol          stop when |phi' - D_bb x| / |phi'| <= tol (recursive residual of CGLS,
+ *                confirmed by an FP64 recomputation at the end)
+ *   maxiter      cap on CG iterations (inner iterations summed for mixed precision)
+ *   inner_prec   DWA_F64: plain FP64 CGLS.  DWA_F32 / DWA_BF16: inner CGLS with fields
+ *                stored in that precision and FP32 arithmetic, inside an FP64 outer loop
+ *                with true-residual recomputation and reliable updates
+ *   delta        reliable-update trigger for mixed precision: the FP64 residual is
+ *                recomputed when the inner residual has fallen by this factor (e.g. 0.1)
+ *   check_every  iterations between convergence reads on the host (>= 1)
+ *   warm_start   non-zero: start from the x passed in instead of 0 */
+typedef struct {
+  double tol;
+  int maxiter;
+  int inner_prec;
+  double delta;
+  int check_every;
+  int warm_start;
+} dwa_solve_opts;
+
+typedef struct {
+  int iters;            /* CG iterations (all precisions) */
+  int outer;            /* FP64 residual recomputations (mixed precision) */
+  int converged;
+  double rel_resid;     /* final |phi' - D_bb x| / |phi'| recomputed in FP64 */
+  double time_ms;       /* wall time of the solve */
+  long long n_Dbb;      /* applications of D_bb or D_bb^dag */
+} dwa_solve_stats;
+
+/* Create a context for one lattice and parameter set on the current device.
+ * Validates: every extent even and >= 2, Ls in [2, 32], alpha != 0, b/c non-null
+ * and finite, and that the site-local matrix I of eq.(redblack) is invertible.
+ * stream is a hipStream_t (NULL = default stream). */
+int dwa_create(dwa_ctx **ctx, const dwa_params *p, void *stream);
+int dwa_destroy(dwa_ctx *ctx);
+
+/* Upload the gauge field: U_dev is canonical complex128 [4][V][3][3] on the device.
+ * The antiperiodic phase is folded into U_t(t = Lt-1) and FP32/BF16 copies are made. */
+int dwa_set_links(dwa_ctx *ctx, const void *U_dev);
+
+/* Bytes of one half-lattice SoA field of precision prec. */
+size_t dwa_field_bytes(const dwa_ctx *ctx, int prec);
+/* Number of sites V and slices Ls of the context (either pointer may be NULL). */
+int dwa_get_sizes(const dwa_ctx *ctx, long long *V, int *Ls);
+
+/* Canonical 5D complex128 [Ls][V][4][3] <-> SoA half field of the given parity
+ * (0 = black/even, 1 = red/odd) and precision.  Unpack writes only the sites of
+ * that parity and leaves the others untouched.  Precision conversion rounds to
+ * nearest even. */
+int dwa_pack_spinor5(dwa_ctx *ctx, int prec, void *dst_soa, const void *src_canon5, int parity);
+int dwa_unpack_spinor5(dwa_ctx *ctx, int prec, void *dst_canon5, const void *src_soa, int parity);
+
+/* out = D_w in on n independent 4D slices (eq.(wilson)); canonical complex128
+ * [n][V][4][3], FP64.  out and in must not overlap. */
+int dwa_apply_Dw(dwa_ctx *ctx, void *out, const void *in, int nslices);
+
+/* out_b = D_bb in_b (eq.(redblack)) and out_b = D_bb^dagger in_b on black SoA fields of
+ * precision prec (FP64, or FP32 / BF16 storage with FP32 arithmetic).  out_b and in_b
+ * must not overlap. */
+int dwa_apply_Dbb(dwa_ctx *ctx, int prec, void *out_b, const void *in_b);
+int dwa_apply_Dbb_dag(dwa_ctx *ctx, int prec, void *out_b, const void *in_b);
+
+/* Solve D_bb x_b = rhs_b by CG on the normal equations (Sec. 3).  x_b and rhs_b are
+ * FP64 black SoA fields.  Returns DWA_OK, DWA_ENOCONV (x_b holds the last iterate) or
+ * DWA_EBREAKDOWN.  stats may be NULL. */
+int dwa_cgne_solve(dwa_ctx *ctx, void *x_b, const void *rhs_b, const dwa_solve_opts *opts,
+                   dwa_solve_stats *stats);
+
+/* The 4D propagator y_1 for a 4D source eta (Sec. 2 and App. B): builds
+ * rho = D_1(1) P (eta, 0, ..., 0), the Schur right-hand side
+ * phi' = I_bb^-1 (rho_b - D_br I_rr^-1 rho_r), solves D_bb psi_b = phi' with
+ * dwa_cgne_solve, reconstructs psi_r = I_rr^-1 (rho_r - D_rb psi_b) and extracts
+ * y_1 = P- psi_1 + P+ psi_Ls.  y1 and eta are canonical complex128 [V][4][3] on the
+ * device.  psi5 (optional, may be NULL) receives the full 5D solution psi, canonical. */
+int dwa_propagator(dwa_ctx *ctx, void *y1, const void *eta, const dwa_solve_opts *opts,
+                   dwa_solve_stats *stats, void *psi5);
+
+const char *dwa_strerror(int status);
+const char *dwa_last_error(void);
+
+/* Host-only (no device needed): the real Ls x Ls fifth-dimension matrices the
+ * kernels apply, per chirality, out = [2][Ls][Ls] (index 0 = P+, 1 = P-).  kind:
+ * 0 identity, 1 B G, 2 N = B I_1^-1, 3 G^-1 I_1^-1, 4 g5 I_1^-T G^-1, 5 N^T,
+ * 6 G B^T g5, 7 I_1^-1, 8 I_1 G (the site-local block I of D_alpha, eq.(redblack)).
+ * Here D_1 = D_w B + C slice by slice, I_1 = (4 + M5) B + C and D_alpha = D_1 G
+ * with G = diag(P- + alpha P+, alpha, ..., alpha, P+ + alpha P-) (Sec. 2). */
+int dwa_debug_smatrix(const dwa_params *p, int kind, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DWA_H */

@@ -1,0 +1,624 @@
+// C-ABI of libdwa: context set-up, operators, CG on the normal equations and the
+// propagator pipeline.  Host code; every arithmetic step runs in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dwa_internal.h"
+
+namespace dwa {
+
+namespace {
+thread_local std::string g_last_error;
+
+constexpr int kBanks = 4;
+static_assert(sizeof(((dwa_ctx*)nullptr)->w64) / sizeof(void*) == W64_COUNT, "w64 slots");
+static_assert(sizeof(((dwa_ctx*)nullptr)->w32) / sizeof(void*) == LOW_COUNT, "w32 slots");
+static_assert(sizeof(((dwa_ctx*)nullptr)->w16) / sizeof(void*) == LOW_COUNT, "w16 slots");
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+  if (e == hipSuccess) return DWA_OK;
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? DWA_ENOMEM : DWA_EHIP;
+}
+
+size_t field_elems(const dwa_ctx* ctx) { return size_t(ctx->Ls) * 12 * size_t(ctx->Vh); }
+
+}  // namespace dwa
+
+using namespace dwa;
+
+namespace {
+
+int einval(const std::string& msg) {
+  set_error(msg);
+  return DWA_EINVAL;
+}
+
+#define DWA_TRY(expr)             \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_ != DWA_OK) return rc_; \
+  } while (0)
+#define DWA_HIP(expr, what) DWA_TRY(hip_fail((expr), what))
+
+void** low_pool(dwa_ctx* ctx, int prec) {
+  if (prec == DWA_F32) return ctx->w32;
+  if (prec == DWA_BF16) return ctx->w16;
+  return ctx->w64;
+}
+
+double* bank(dwa_ctx* ctx, int i) { return ctx->d_partials + size_t(i) * ctx->partials_per_bank; }
+
+bool valid_prec(int prec) { return prec == DWA_F64 || prec == DWA_F32 || prec == DWA_BF16; }
+
+// ---------------------------------------------------------------------------
+// operator building blocks.  Fields are black SoA of precision prec; tb / tr are
+// workspace vectors (black / red) of the same precision.
+
+// out = in - 1/4 G^-1 I^-1 H_br N H_rb (B G in); u is the premixed input B G in.
+int dbb_from_premix(dwa_ctx* ctx, int prec, void* out, const void* in, const void* u, void* tr,
+                    double* partials, int* nblocks) {
+  HopOp a{u, tr, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_N, 1, ctx->Ls, nullptr};
+  DWA_TRY(launch_hop(ctx, prec, a, nullptr));
+  HopOp b{tr, out, nullptr, in, -0.25, 0.0, 1.0, MIX_GINV_IINV, 0, ctx->Ls, partials};
+  return launch_hop(ctx, prec, b, nblocks);
+}
+
+// out = in - 1/4 G B^T g5 H_br N^T H_rb w; w is the premixed input g5 I^-T G^-1 in.
+int dbbdag_from_premix(dwa_ctx* ctx, int prec, void* out, const void* in, const void* w, void* tr,
+                       double* partials, int* nblocks) {
+  HopOp a{w, tr, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_NT, 1, ctx->Ls, nullptr};
+  DWA_TRY(launch_hop(ctx, prec, a, nullptr));
+  HopOp b{tr, out, nullptr, in, -0.25, 0.0, 1.0, MIX_G_BT_G5, 0, ctx->Ls, partials};
+  return launch_hop(ctx, prec, b, nblocks);
+}
+
+int apply_dbb(dwa_ctx* ctx, int prec, void* out, const void* in, void* tb, void* tr) {
+  DWA_TRY(launch_smix(ctx, prec, MIX_BG, tb, in, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  return dbb_from_premix(ctx, prec, out, in, tb, tr, nullptr, nullptr);
+}
+
+int apply_dbbdag(dwa_ctx* ctx, int prec, void* out, const void* in, void* tb, void* tr) {
+  DWA_TRY(launch_smix(ctx, prec, MIX_G5_IINVT_GINV, tb, in, nullptr, 0.0, ctx->Ls, nullptr,
+                      nullptr));
+  return dbbdag_from_premix(ctx, prec, out, in, tb, tr, nullptr, nullptr);
+}
+
+int read_scalars(dwa_ctx* ctx) {
+  DWA_HIP(hipMemcpyAsync(ctx->h_scal, ctx->d_scal, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                         ctx->stream),
+          "scalar readback");
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "stream sync");
+  return DWA_OK;
+}
+
+// |v|^2 of a field into a host double (synchronising)
+int host_norm2(dwa_ctx* ctx, int prec, const void* v, double* out) {
+  int nb = 0;
+  DWA_TRY(launch_norm2(ctx, prec, v, field_elems(ctx), bank(ctx, 3), &nb));
+  DWA_TRY(launch_sum_partials(ctx, bank(ctx, 3), nb, ctx->d_red));
+  DWA_HIP(hipMemcpyAsync(out, ctx->d_red, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+          "norm readback");
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "stream sync");
+  return DWA_OK;
+}
+
+// CGLS on D_bb of precision prec with the workspace pool of that precision.
+// x (in/out) and rhs are fields of precision prec.  Stops when the recursive
+// residual satisfies |r|^2 <= tol^2 |rhs|^2 or after maxiter iterations.
+struct CgResult {
+  int iters = 0;
+  int converged = 0;
+  int breakdown = 0;
+  double rel_recursive = 0.0;
+  long long n_dbb = 0;
+};
+
+int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol, int maxiter,
+         int check_every, CgResult* res) {
+  void** W = low_pool(ctx, prec);
+  const bool p64 = prec == DWA_F64;
+  void* r = W[p64 ? W_R : L_R];
+  void* p = W[p64 ? W_P : L_P];
+  void* z = W[p64 ? W_Z : L_Z];
+  void* q = W[p64 ? W_Q : L_Q];
+  void* w = W[p64 ? W_W : L_W];
+  void* u = W[p64 ? W_U : L_U];
+  void* t = W[p64 ? W_T : L_T];
+  const size_t n = field_elems(ctx);
+  DevScalars* sc = ctx->d_scal;
+  int nbA = 0, nbB = 0;
+  if (check_every < 1) check_every = 1;
+
+  if (warm) {
+    DWA_TRY(apply_dbb(ctx, prec, q, x, u, t));
+    DWA_TRY(launch_axpby(ctx, prec, r, 1.0, rhs, 0.0, n));
+    DWA_TRY(launch_axpby(ctx, prec, r, -1.0, q, 1.0, n));
+    res->n_dbb += 1;
+  } else {
+    DWA_TRY(launch_zero(ctx, prec, x, n));
+    DWA_TRY(launch_axpby(ctx, prec, r, 1.0, rhs, 0.0, n));
+  }
+  // z = D_bb^dag r, gamma = |z|^2, |rhs|^2
+  DWA_TRY(launch_smix(ctx, prec, MIX_G5_IINVT_GINV, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  DWA_TRY(dbbdag_from_premix(ctx, prec, z, r, w, t, bank(ctx, 0), &nbA));
+  DWA_TRY(launch_norm2(ctx, prec, rhs, n, bank(ctx, 1), &nbB));
+  DWA_TRY(launch_cg_finalize(ctx, 2, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
+  if (warm) {
+    DWA_TRY(launch_norm2(ctx, prec, r, n, bank(ctx, 1), &nbB));
+    DWA_TRY(launch_cg_finalize(ctx, 4, sc, bank(ctx, 1), nbB, nullptr, 0));
+  }
+  res->n_dbb += 1;
+  DWA_TRY(launch_axpby(ctx, prec, p, 1.0, z, 0.0, n));
+  DWA_TRY(launch_smix(ctx, prec, MIX_BG, u, p, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+
+  const double tol2 = tol * tol;
+  int k = 0;
+  for (;;) {
+    if (k % check_every == 0 || k >= maxiter) {
+      DWA_TRY(read_scalars(ctx));
+      const DevScalars& h = *ctx->h_scal;
+      if (h.flags) {
+        res->breakdown = 1;
+        break;
+      }
+      res->rel_recursive = h.b2 > 0 ? std::sqrt(h.rr / h.b2) : 0.0;
+      if (h.b2 == 0.0 || h.rr <= tol2 * h.b2) {
+        res->converged = 1;
+        break;
+      }
+      if (k >= maxiter) break;
+    }
+    // q = D_bb p (premixed u = B G p), |q|^2, a = gamma / |q|^2
+    DWA_TRY(dbb_from_premix(ctx, prec, q, p, u, t, bank(ctx, 0), &nbA));
+    DWA_TRY(launch_cg_finalize(ctx, 0, sc, bank(ctx, 0), nbA, nullptr, 0));
+    // x += a p ; r -= a q ; |r|^2 ; w = g5 I^-T G^-1 r
+    DWA_TRY(launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB));
+    // z = D_bb^dag r, beta = |z|^2 / gamma
+    DWA_TRY(dbbdag_from_premix(ctx, prec, z, r, w, t, bank(ctx, 0), &nbA));
+    DWA_TRY(launch_cg_finalize(ctx, 1, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
+    // p = z + beta p ; u = B G p
+    DWA_TRY(launch_cg_update2(ctx, prec, p, u, z, sc));
+    res->n_dbb += 2;
+    ++k;
+  }
+  res->iters = k;
+  return DWA_OK;
+}
+
+// |rhs - D_bb x| / |rhs| in FP64 (uses W_Q, W_RES, W_OPB, W_OPR)
+int true_residual64(dwa_ctx* ctx, const void* x, const void* rhs, double rhs_norm, double* rel,
+                    void* res_out) {
+  void** W = ctx->w64;
+  const size_t n = field_elems(ctx);
+  DWA_TRY(apply_dbb(ctx, DWA_F64, W[W_Q], x, W[W_OPB], W[W_OPR]));
+  void* r = res_out ? res_out : W[W_RES];
+  DWA_TRY(launch_axpby(ctx, DWA_F64, r, 1.0, rhs, 0.0, n));
+  DWA_TRY(launch_axpby(ctx, DWA_F64, r, -1.0, W[W_Q], 1.0, n));
+  double rr = 0.0;
+  DWA_TRY(host_norm2(ctx, DWA_F64, r, &rr));
+  *rel = rhs_norm > 0 ? std::sqrt(rr) / rhs_norm : 0.0;
+  return DWA_OK;
+}
+
+// Mixed precision: FP64 outer defect correction around an inner CGLS in storage
+// precision inner (F32 or BF16, FP32 arithmetic).  Each outer step recomputes the
+// true FP64 residual r = rhs - D_bb x, solves D_bb e = r / |r| in low precision to a
+// relative residual delta, and accumulates x += |r| e in FP64.
+int mixed_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_solve_opts* o,
+                dwa_solve_stats* st) {
+  void** W = ctx->w64;
+  void** L = low_pool(ctx, inner);
+  const size_t n = field_elems(ctx);
+  double b2 = 0.0;
+  DWA_TRY(host_norm2(ctx, DWA_F64, rhs, &b2));
+  const double bnorm = std::sqrt(b2);
+  if (!o->warm_start) DWA_TRY(launch_zero(ctx, DWA_F64, x, n));
+  if (bnorm == 0.0) {
+    st->converged = 1;
+    st->rel_resid = 0.0;
+    return DWA_OK;
+  }
+  const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
+  int total = 0;
+  long long ndbb = 0;
+  int outer = 0;
+  double rel = 1.0;
+  // first residual
+  if (o->warm_start) {
+    DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
+    ndbb += 1;
+  } else {
+    DWA_TRY(launch_axpby(ctx, DWA_F64, W[W_RES], 1.0, rhs, 0.0, n));
+    rel = 1.0;
+  }
+  int status = DWA_OK;
+  double prev_rel = rel;
+  int stall = 0;
+  while (rel > o->tol) {
+    if (total >= o->maxiter) {
+      status = DWA_ENOCONV;
+      break;
+    }
+    const double rnorm = rel * bnorm;
+    // low-precision rhs: r / |r|
+    DWA_TRY(launch_convert(ctx, inner, L[L_OPB], DWA_F64, W[W_RES], n, 1.0 / rnorm));
+    // inner target: delta, but not tighter than needed for the final tolerance
+    double inner_tol = delta;
+    const double need = 0.5 * o->tol / rel;
+    if (need > inner_tol) inner_tol = need;
+    CgResult cr;
+    DWA_TRY(cgls(ctx, inner, L[L_X], L[L_OPB], false, inner_tol, o->maxiter - total,
+                 o->check_every, &cr));
+    total += cr.iters;
+    ndbb += cr.n_dbb;
+    if (cr.breakdown && cr.iters == 0) {
+      status = DWA_EBREAKDOWN;
+      break;
+    }
+    // x += |r| e  (FP64 accumulate)
+    DWA_TRY(launch_convert(ctx, DWA_F64, W[W_OPB], inner, L[L_X], n, rnorm));
+    DWA_TRY(launch_axpby(ctx, DWA_F64, x, 1.0, W[W_OPB], 1.0, n));
+    DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
+    ndbb += 1;
+    ++outer;
+    if (!(rel < 0.9 * prev_rel)) {
+      if (++stall >= 3) {
+        status = DWA_ENOCONV;
+        break;
+      }
+    } else {
+      stall = 0;
+    }
+    prev_rel = rel;
+  }
+  st->iters = total;
+  st->outer = outer;
+  st->converged = rel <= o->tol;
+  st->rel_resid = rel;
+  st->n_Dbb = ndbb;
+  return status;
+}
+
+int check_ctx(dwa_ctx* ctx) {
+  if (!ctx) return einval("null context");
+  if (!ctx->links_set) {
+    set_error("links not set (call dwa_set_links first)");
+    return DWA_ESTATE;
+  }
+  return DWA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dwa_strerror(int status) {
+  switch (status) {
+    case DWA_OK: return "ok";
+    case DWA_EINVAL: return "invalid argument";
+    case DWA_ENOMEM: return "device out of memory";
+    case DWA_EHIP: return "HIP runtime error";
+    case DWA_ENOCONV: return "solver did not converge";
+    case DWA_EBREAKDOWN: return "CG breakdown";
+    case DWA_ENAN: return "non-finite input";
+    case DWA_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+const char* dwa_last_error(void) { return dwa::g_last_error.c_str(); }
+
+int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
+  if (!out) return einval("null output pointer");
+  *out = nullptr;
+  if (!p) return einval("null params");
+  for (int d = 0; d < 4; ++d)
+    if (p->dims[d] < 2 || (p->dims[d] & 1))
+      return einval("every lattice extent must be even and >= 2");
+  if (p->Ls < 2 || p->Ls > 32) return einval("Ls must be in [2, 32]");
+  if (!p->b || !p->c) return einval("null b or c");
+  if (!std::isfinite(p->alpha) || p->alpha == 0.0) return einval("alpha must be finite and non-zero");
+  if (!std::isfinite(p->M5) || !std::isfinite(p->m)) return einval("M5 and m must be finite");
+  for (int s = 0; s < p->Ls; ++s)
+    if (!std::isfinite(p->b[s]) || !std::isfinite(p->c[s])) return einval("b, c must be finite");
+  const long long V = (long long)p->dims[0] * p->dims[1] * p->dims[2] * p->dims[3];
+  if ((long long)p->Ls * 12 * V > (1LL << 31) - 1) return einval("field too large for 32-bit indexing");
+  std::vector<double> mix;
+  std::string err;
+  if (!build_smatrices(p->Ls, p->M5, p->m, p->alpha, p->b, p->c, mix, err)) return einval(err);
+
+  dwa_ctx* ctx = new dwa_ctx();
+  for (int d = 0; d < 4; ++d) ctx->dims[d] = p->dims[d];
+  ctx->Ls = p->Ls;
+  ctx->V = V;
+  ctx->Vh = V / 2;
+  ctx->M5 = p->M5;
+  ctx->m = p->m;
+  ctx->alpha = p->alpha;
+  ctx->b.assign(p->b, p->b + p->Ls);
+  ctx->c.assign(p->c, p->c + p->Ls);
+  ctx->antiperiodic_t = p->antiperiodic_t ? 1 : 0;
+  ctx->stream = (hipStream_t)stream;
+  ctx->h_mix = mix;
+
+  auto fail = [&](int rc) {
+    dwa_destroy(ctx);
+    return rc;
+  };
+  int rc = hip_fail(hipGetDevice(&ctx->device), "hipGetDevice");
+  if (rc) return fail(rc);
+
+  // geometry: checkerboard <-> lexicographic and neighbour tables
+  const int Lx = p->dims[0], Ly = p->dims[1], Lz = p->dims[2], Lt = p->dims[3];
+  const long long Vh = ctx->Vh;
+  std::vector<int> cb2lex(2 * Vh), nbr(size_t(16) * Vh);
+  for (long long lex = 0; lex < V; ++lex) {
+    long long r = lex;
+    int x = r % Lx; r /= Lx;
+    int y = r % Ly; r /= Ly;
+    int z = r % Lz;
+    int t = (int)(r / Lz);
+    int par = (x + y + z + t) & 1;
+    cb2lex[par * Vh + lex / 2] = (int)lex;
+  }
+  for (int par = 0; par < 2; ++par)
+    for (long long cb = 0; cb < Vh; ++cb) {
+      long long lex = cb2lex[par * Vh + cb];
+      long long r = lex;
+      int c4[4];
+      c4[0] = r % Lx; r /= Lx;
+      c4[1] = r % Ly; r /= Ly;
+      c4[2] = r % Lz;
+      c4[3] = (int)(r / Lz);
+      for (int dir = 0; dir < 8; ++dir) {
+        int mu = dir & 3, step = dir < 4 ? 1 : -1;
+        int n4[4] = {c4[0], c4[1], c4[2], c4[3]};
+        n4[mu] = (n4[mu] + step + p->dims[mu]) % p->dims[mu];
+        long long nlex = n4[0] + (long long)Lx * (n4[1] + (long long)Ly * (n4[2] + (long long)Lz * n4[3]));
+        nbr[(size_t(par) * 8 + dir) * Vh + cb] = (int)(nlex / 2);
+      }
+    }
+  if ((rc = hip_fail(hipMalloc(&ctx->d_cb2lex, sizeof(int) * cb2lex.size()), "alloc cb2lex")))
+    return fail(rc);
+  if ((rc = hip_fail(hipMalloc(&ctx->d_nbr, sizeof(int) * nbr.size()), "alloc nbr"))) return fail(rc);
+  if ((rc = hip_fail(hipMemcpy(ctx->d_cb2lex, cb2lex.data(), sizeof(int) * cb2lex.size(),
+                               hipMemcpyHostToDevice), "upload cb2lex")))
+    return fail(rc);
+  if ((rc = hip_fail(hipMemcpy(ctx->d_nbr, nbr.data(), sizeof(int) * nbr.size(),
+                               hipMemcpyHostToDevice), "upload nbr")))
+    return fail(rc);
+  // s-matrices
+  std::vector<float> mix32(mix.begin(), mix.end());
+  if ((rc = hip_fail(hipMalloc(&ctx->d_mix64, sizeof(double) * mix.size()), "alloc mix"))) return fail(rc);
+  if ((rc = hip_fail(hipMalloc(&ctx->d_mix32, sizeof(float) * mix.size()), "alloc mix32"))) return fail(rc);
+  if ((rc = hip_fail(hipMemcpy(ctx->d_mix64, mix.data(), sizeof(double) * mix.size(), hipMemcpyHostToDevice), "upload mix")))
+    return fail(rc);
+  if ((rc = hip_fail(hipMemcpy(ctx->d_mix32, mix32.data(), sizeof(float) * mix32.size(), hipMemcpyHostToDevice), "upload mix32")))
+    return fail(rc);
+  // links and workspace
+  const size_t n = field_elems(ctx);
+  for (int pr = 0; pr < 3; ++pr)
+    if ((rc = hip_fail(hipMalloc(&ctx->prec[pr].links, elem_bytes(pr) * 2 * 4 * 9 * Vh), "alloc links")))
+      return fail(rc);
+  for (int i = 0; i < W64_COUNT; ++i)
+    if ((rc = hip_fail(hipMalloc(&ctx->w64[i], 16 * n), "alloc fp64 workspace"))) return fail(rc);
+  for (int i = 0; i < LOW_COUNT; ++i) {
+    if ((rc = hip_fail(hipMalloc(&ctx->w32[i], 8 * n), "alloc fp32 workspace"))) return fail(rc);
+    if ((rc = hip_fail(hipMalloc(&ctx->w16[i], 4 * n), "alloc bf16 workspace"))) return fail(rc);
+  }
+  ctx->partials_per_bank = size_t(Vh) + 8192;
+  if ((rc = hip_fail(hipMalloc(&ctx->d_partials, sizeof(double) * kBanks * ctx->partials_per_bank), "alloc partials")))
+    return fail(rc);
+  if ((rc = hip_fail(hipMalloc(&ctx->d_scal, sizeof(DevScalars)), "alloc scalars"))) return fail(rc);
+  if ((rc = hip_fail(hipHostMalloc(&ctx->h_scal, sizeof(DevScalars), hipHostMallocDefault), "alloc pinned")))
+    return fail(rc);
+  if ((rc = hip_fail(hipMalloc(&ctx->d_red, sizeof(double) * 8), "alloc red"))) return fail(rc);
+  if ((rc = hip_fail(hipMemset(ctx->d_scal, 0, sizeof(DevScalars)), "clear scalars"))) return fail(rc);
+  *out = ctx;
+  return DWA_OK;
+}
+
+int dwa_destroy(dwa_ctx* ctx) {
+  if (!ctx) return DWA_OK;
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(ctx->d_nbr);
+  f(ctx->d_cb2lex);
+  f(ctx->d_mix64);
+  f(ctx->d_mix32);
+  for (auto& pr : ctx->prec) f(pr.links);
+  for (auto p : ctx->w64) f(p);
+  for (auto p : ctx->w32) f(p);
+  for (auto p : ctx->w16) f(p);
+  f(ctx->d_partials);
+  f(ctx->d_scal);
+  f(ctx->d_red);
+  if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
+  delete ctx;
+  return DWA_OK;
+}
+
+int dwa_set_links(dwa_ctx* ctx, const void* U) {
+  if (!ctx) return einval("null context");
+  if (!U) return einval("null links");
+  for (int pr = 0; pr < 3; ++pr) DWA_TRY(launch_pack_links(ctx, pr, ctx->prec[pr].links, U));
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "set links sync");
+  ctx->links_set = true;
+  return DWA_OK;
+}
+
+size_t dwa_field_bytes(const dwa_ctx* ctx, int prec) {
+  if (!ctx || !valid_prec(prec)) return 0;
+  return elem_bytes(prec) * field_elems(ctx);
+}
+
+int dwa_get_sizes(const dwa_ctx* ctx, long long* V, int* Ls) {
+  if (!ctx) return einval("null context");
+  if (V) *V = ctx->V;
+  if (Ls) *Ls = ctx->Ls;
+  return DWA_OK;
+}
+
+int dwa_pack_spinor5(dwa_ctx* ctx, int prec, void* dst, const void* src, int parity) {
+  if (!ctx) return einval("null context");
+  if (!dst || !src) return einval("null field");
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (parity != 0 && parity != 1) return einval("parity must be 0 or 1");
+  return launch_pack5(ctx, prec, dst, src, parity, ctx->Ls);
+}
+
+int dwa_unpack_spinor5(dwa_ctx* ctx, int prec, void* dst, const void* src, int parity) {
+  if (!ctx) return einval("null context");
+  if (!dst || !src) return einval("null field");
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (parity != 0 && parity != 1) return einval("parity must be 0 or 1");
+  return launch_unpack5(ctx, prec, dst, src, parity, ctx->Ls);
+}
+
+int dwa_apply_Dw(dwa_ctx* ctx, void* out, const void* in, int nslices) {
+  DWA_TRY(check_ctx(ctx));
+  if (!out || !in) return einval("null field");
+  if (nslices < 1) return einval("nslices must be >= 1");
+  void** W = ctx->w64;
+  const size_t vol12 = size_t(ctx->V) * 12;
+  for (int s0 = 0; s0 < nslices; s0 += ctx->Ls) {
+    const int ns = (nslices - s0) < ctx->Ls ? (nslices - s0) : ctx->Ls;
+    const double2* src = (const double2*)in + s0 * vol12;
+    double2* dst = (double2*)out + s0 * vol12;
+    DWA_TRY(launch_pack5(ctx, DWA_F64, W[W_OPB], src, 0, ns));
+    DWA_TRY(launch_pack5(ctx, DWA_F64, W[W_OPR], src, 1, ns));
+    // out_p = (4 + M5) in_p - 1/2 H in_{1-p}
+    HopOp hb{W[W_OPR], W[W_CHI_B], W[W_OPB], nullptr, -0.5, 4.0 + ctx->M5, 0.0, MIX_IDENTITY, 0, ns, nullptr};
+    HopOp hr{W[W_OPB], W[W_CHI_R], W[W_OPR], nullptr, -0.5, 4.0 + ctx->M5, 0.0, MIX_IDENTITY, 1, ns, nullptr};
+    DWA_TRY(launch_hop(ctx, DWA_F64, hb, nullptr));
+    DWA_TRY(launch_hop(ctx, DWA_F64, hr, nullptr));
+    DWA_TRY(launch_unpack5(ctx, DWA_F64, dst, W[W_CHI_B], 0, ns));
+    DWA_TRY(launch_unpack5(ctx, DWA_F64, dst, W[W_CHI_R], 1, ns));
+  }
+  return DWA_OK;
+}
+
+int dwa_apply_Dbb(dwa_ctx* ctx, int prec, void* out, const void* in) {
+  DWA_TRY(check_ctx(ctx));
+  if (!out || !in) return einval("null field");
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (out == in) return einval("out and in must not overlap");
+  void** W = low_pool(ctx, prec);
+  const bool p64 = prec == DWA_F64;
+  return apply_dbb(ctx, prec, out, in, W[p64 ? W_OPB : L_OPB], W[p64 ? W_OPR : L_OPR]);
+}
+
+int dwa_apply_Dbb_dag(dwa_ctx* ctx, int prec, void* out, const void* in) {
+  DWA_TRY(check_ctx(ctx));
+  if (!out || !in) return einval("null field");
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (out == in) return einval("out and in must not overlap");
+  void** W = low_pool(ctx, prec);
+  const bool p64 = prec == DWA_F64;
+  return apply_dbbdag(ctx, prec, out, in, W[p64 ? W_OPB : L_OPB], W[p64 ? W_OPR : L_OPR]);
+}
+
+int dwa_cgne_solve(dwa_ctx* ctx, void* x, const void* rhs, const dwa_solve_opts* o,
+                   dwa_solve_stats* stats) {
+  DWA_TRY(check_ctx(ctx));
+  if (!x || !rhs || !o) return einval("null argument");
+  if (!(o->tol >= 0.0) || o->maxiter < 0) return einval("bad tolerance or maxiter");
+  if (!valid_prec(o->inner_prec)) return einval("bad inner precision");
+  if (x == rhs) return einval("x and rhs must not overlap");
+  dwa_solve_stats st{};
+  const auto t0 = std::chrono::steady_clock::now();
+  int status = DWA_OK;
+  if (o->inner_prec == DWA_F64) {
+    CgResult cr;
+    DWA_TRY(cgls(ctx, DWA_F64, x, rhs, o->warm_start != 0, o->tol, o->maxiter, o->check_every, &cr));
+    double b2 = 0.0;
+    DWA_TRY(host_norm2(ctx, DWA_F64, rhs, &b2));
+    double rel = 0.0;
+    DWA_TRY(true_residual64(ctx, x, rhs, std::sqrt(b2), &rel, nullptr));
+    st.iters = cr.iters;
+    st.outer = 0;
+    st.converged = cr.converged;
+    st.rel_resid = rel;
+    st.n_Dbb = cr.n_dbb + 1;
+    if (cr.breakdown) status = DWA_EBREAKDOWN;
+    else if (!cr.converged) status = DWA_ENOCONV;
+  } else {
+    status = mixed_solve(ctx, o->inner_prec, x, rhs, o, &st);
+    if (status != DWA_OK && status != DWA_ENOCONV && status != DWA_EBREAKDOWN) return status;
+  }
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "solve sync");
+  st.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  if (status == DWA_ENOCONV) set_error("solver reached maxiter or stagnated");
+  if (status == DWA_EBREAKDOWN) set_error("CG breakdown (|D_bb p|^2 or |D_bb^dag r|^2 not positive/finite)");
+  return status;
+}
+
+int dwa_propagator(dwa_ctx* ctx, void* y1, const void* eta, const dwa_solve_opts* o,
+                   dwa_solve_stats* stats, void* psi5) {
+  DWA_TRY(check_ctx(ctx));
+  if (!y1 || !eta || !o) return einval("null argument");
+  void** W = ctx->w64;
+  // reject non-finite sources before any arithmetic
+  int* d_flag = reinterpret_cast<int*>(ctx->d_red);
+  DWA_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), ctx->stream), "clear flag");
+  DWA_TRY(launch_check_finite(ctx, eta, size_t(ctx->V) * 12, d_flag));
+  int h_flag = 0;
+  DWA_HIP(hipMemcpyAsync(&h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "flag readback");
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "flag sync");
+  if (h_flag) {
+    set_error("source contains NaN or Inf");
+    return DWA_ENAN;
+  }
+  const int Ls = ctx->Ls;
+  // rho = D_1(1) P (eta, 0, ..., 0): wall slices only
+  DWA_TRY(launch_source(ctx, W[W_CHI_B], W[W_CHI_R], W[W_RHO_B], W[W_RHO_R], eta));
+  HopOp hb{W[W_CHI_R], W[W_RHO_B], W[W_RHO_B], nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 0, Ls, nullptr};
+  HopOp hr{W[W_CHI_B], W[W_RHO_R], W[W_RHO_R], nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 1, Ls, nullptr};
+  DWA_TRY(launch_hop(ctx, DWA_F64, hb, nullptr));
+  DWA_TRY(launch_hop(ctx, DWA_F64, hr, nullptr));
+  // phi' = I_bb^-1 (rho_b - D_br I_rr^-1 rho_r) = G^-1 I^-1 (rho_b + 1/2 H_br N rho_r)
+  DWA_TRY(launch_smix(ctx, DWA_F64, MIX_N, W[W_T], W[W_RHO_R], nullptr, 0.0, Ls, nullptr, nullptr));
+  HopOp prep{W[W_T], W[W_PHI], W[W_RHO_B], nullptr, 0.5, 1.0, 0.0, MIX_GINV_IINV, 0, Ls, nullptr};
+  DWA_TRY(launch_hop(ctx, DWA_F64, prep, nullptr));
+  // D_bb psi_b = phi'
+  dwa_solve_opts so = *o;
+  so.warm_start = 0;
+  int status = dwa_cgne_solve(ctx, W[W_PSI_B], W[W_PHI], &so, stats);
+  if (status != DWA_OK && status != DWA_ENOCONV) return status;
+  // psi_r = I_rr^-1 (rho_r - D_rb psi_b) = G^-1 I^-1 (rho_r + 1/2 H_rb B G psi_b)
+  DWA_TRY(launch_smix(ctx, DWA_F64, MIX_BG, W[W_OPB], W[W_PSI_B], nullptr, 0.0, Ls, nullptr, nullptr));
+  HopOp rec{W[W_OPB], W[W_PSI_R], W[W_RHO_R], nullptr, 0.5, 1.0, 0.0, MIX_GINV_IINV, 1, Ls, nullptr};
+  DWA_TRY(launch_hop(ctx, DWA_F64, rec, nullptr));
+  DWA_TRY(launch_extract(ctx, y1, W[W_PSI_B], W[W_PSI_R]));
+  if (psi5) {
+    DWA_TRY(launch_unpack5(ctx, DWA_F64, psi5, W[W_PSI_B], 0, Ls));
+    DWA_TRY(launch_unpack5(ctx, DWA_F64, psi5, W[W_PSI_R], 1, Ls));
+  }
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "propagator sync");
+  return status;
+}
+
+// Host-only access to the site-local matrices (no device needed); used to check
+// the fifth-dimension algebra on the CPU.  out receives [2][Ls][Ls].
+int dwa_debug_smatrix(const dwa_params* p, int kind, double* out) {
+  if (!p || !out || !p->b || !p->c) return einval("null argument");
+  if (kind < 0 || kind >= MIX_COUNT) return einval("bad matrix kind");
+  std::vector<double> mix;
+  std::string err;
+  if (!build_smatrices(p->Ls, p->M5, p->m, p->alpha, p->b, p->c, mix, err)) return einval(err);
+  std::memcpy(out, &mix[size_t(kind) * 2 * p->Ls * p->Ls], sizeof(double) * 2 * p->Ls * p->Ls);
+  return DWA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Internal declarations of libdwa: storage types, the context, host helpers and
+// kernel launchers.  Everything here is gfx950 (CDNA4, wave64) HIP.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dwa.h"
+
+namespace dwa {
+
+// ----------------------------------------------------------------------------
+// complex arithmetic in the compute precision R (double for FP64 fields, float
+// for FP32 and BF16 storage)
+template <typename R>
+struct cpx {
+  R re, im;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ cpx<R> cmk(R a, R b) { return cpx<R>{a, b}; }
+template <typename R>
+__host__ __device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cpx<R> operator*(R s, cpx<R> a) { return {s * a.re, s * a.im}; }
+// i*a and -i*a
+template <typename R>
+__host__ __device__ __forceinline__ cpx<R> mul_i(cpx<R> a) { return {-a.im, a.re}; }
+template <typename R>
+__host__ __device__ __forceinline__ cpx<R> mul_mi(cpx<R> a) { return {a.im, -a.re}; }
+// acc += u * v, acc += conj(u) * v
+template <typename R>
+__host__ __device__ __forceinline__ void cmac(cpx<R>& acc, cpx<R> u, cpx<R> v) {
+  acc.re = fma(u.re, v.re, acc.re);
+  acc.re = fma(-u.im, v.im, acc.re);
+  acc.im = fma(u.re, v.im, acc.im);
+  acc.im = fma(u.im, v.re, acc.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ void cmac_conj(cpx<R>& acc, cpx<R> u, cpx<R> v) {
+  acc.re = fma(u.re, v.re, acc.re);
+  acc.re = fma(u.im, v.im, acc.re);
+  acc.im = fma(u.re, v.im, acc.im);
+  acc.im = fma(-u.im, v.re, acc.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ R norm2(cpx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// ----------------------------------------------------------------------------
+// storage traits: how one complex number of a field is held in HBM
+struct F64 {
+  using real = double;
+  using elem = double2;
+  static constexpr int prec = DWA_F64;
+};
+struct F32 {
+  using real = float;
+  using elem = float2;
+  static constexpr int prec = DWA_F32;
+};
+struct BF16 {  // bf16 real part in the low half, bf16 imaginary part in the high half
+  using real = float;
+  using elem = uint32_t;
+  static constexpr int prec = DWA_BF16;
+};
+
+__host__ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) {  // inf or nan: keep, force a quiet nan payload
+    return (u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u);
+  }
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__host__ __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+template <typename S>
+__device__ __forceinline__ cpx<typename S::real> ld(const typename S::elem* p, size_t i);
+template <>
+__device__ __forceinline__ cpx<double> ld<F64>(const double2* p, size_t i) {
+  double2 v = p[i];
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ cpx<float> ld<F32>(const float2* p, size_t i) {
+  float2 v = p[i];
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ cpx<float> ld<BF16>(const uint32_t* p, size_t i) {
+  uint32_t v = p[i];
+  return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
+}
+
+template <typename S>
+__device__ __forceinline__ void st(typename S::elem* p, size_t i, cpx<typename S::real> v);
+template <>
+__device__ __forceinline__ void st<F64>(double2* p, size_t i, cpx<double> v) { p[i] = make_double2(v.re, v.im); }
+template <>
+__device__ __forceinline__ void st<F32>(float2* p, size_t i, cpx<float> v) { p[i] = make_float2(v.re, v.im); }
+template <>
+__device__ __forceinline__ void st<BF16>(uint32_t* p, size_t i, cpx<float> v) {
+  p[i] = f32_to_bf16_rne(v.re) | (f32_to_bf16_rne(v.im) << 16);
+}
+
+inline size_t elem_bytes(int prec) { return prec == DWA_F64 ? 16 : (prec == DWA_F32 ? 8 : 4); }
+
+// ----------------------------------------------------------------------------
+// site-local fifth-dimension operators.  Each is a real Ls x Ls matrix per
+// chirality (index 0 = P+, spins 0,1; index 1 = P-, spins 2,3), stored [2][Ls][Ls].
+enum MixKind {
+  MIX_IDENTITY = 0,
+  MIX_BG,          // B G           : premix of the D_bb input
+  MIX_N,           // N = B I^-1    : after the first hop of D_bb
+  MIX_GINV_IINV,   // G^-1 I^-1     : after the second hop of D_bb, Schur prep, reconstruction
+  MIX_G5_IINVT_GINV,  // g5 I^-T G^-1 : premix of the D_bb^dag input
+  MIX_NT,          // N^T           : after the first hop of D_bb^dag
+  MIX_G_BT_G5,     // G B^T g5      : after the second hop of D_bb^dag
+  MIX_IINV,        // I^-1 (alpha = 1 part only, used by tests)
+  MIX_I_ALPHA,     // I_1 G         : the site-local block I of D_alpha (tests)
+  MIX_COUNT
+};
+
+// Host construction (FP64) of all site-local matrices; returns false and a
+// message when the site-local block I is singular or badly conditioned.
+bool build_smatrices(int Ls, double M5, double m, double alpha, const double* b, const double* c,
+                     std::vector<double>& out /* [MIX_COUNT][2][Ls][Ls] */, std::string& err);
+
+// ----------------------------------------------------------------------------
+// device-side solver scalars
+struct DevScalars {
+  double gamma;   // |z|^2 of the current CGLS step
+  double a;       // step length
+  double beta;
+  double qq;      // |D_bb p|^2
+  double zz;      // |D_bb^dag r|^2
+  double rr;      // |r|^2 (recursive residual)
+  double b2;      // |rhs|^2
+  double aux;     // spare
+  int flags;      // bit 0: |q|^2 not positive/finite; bit 1: |z|^2 not finite
+  int pad[3];
+};
+
+struct PrecFields {  // one precision's copy of the links
+  void* links = nullptr;  // [2][4][9][Vh] elems, boundary phase folded
+};
+
+// FP64 workspace roles (black fields unless noted)
+enum W64Role {
+  W_R = 0, W_P, W_Z, W_Q, W_W, W_U, W_T /* red */, W_X, W_OPB, W_OPR /* red */,
+  W_RHO_B, W_RHO_R /* red */, W_CHI_B, W_CHI_R /* red */, W_PHI, W_PSI_B, W_PSI_R /* red */,
+  W_RES,
+  W64_COUNT
+};
+// low-precision (F32 or BF16 storage) workspace roles
+enum LowRole { L_R = 0, L_P, L_Z, L_Q, L_W, L_U, L_T /* red */, L_X, L_OPB, L_OPR /* red */, LOW_COUNT };
+
+}  // namespace dwa
+
+struct dwa_ctx {
+  int dims[4];
+  int Ls;
+  long long V, Vh;
+  double M5, m, alpha;
+  std::vector<double> b, c;
+  int antiperiodic_t;
+  hipStream_t stream;
+  int device;
+  bool links_set = false;
+
+  // geometry
+  int* d_nbr = nullptr;   // [2][8][Vh] neighbour cb index for an output site of parity p
+  int* d_cb2lex = nullptr;  // [2][Vh]
+  // s-matrices (FP64 and FP32 copies), [MIX_COUNT][2][Ls][Ls]
+  double* d_mix64 = nullptr;
+  float* d_mix32 = nullptr;
+  std::vector<double> h_mix;
+  // links per precision
+  dwa::PrecFields prec[3];
+  // FP64 workspace, one vector per W64Role
+  void* w64[dwa::W64_COUNT] = {nullptr};
+  // low-precision workspace for the inner solver (F32 or BF16 storage), one per LowRole
+  void* w32[dwa::LOW_COUNT] = {nullptr};
+  void* w16[dwa::LOW_COUNT] = {nullptr};
+  double* d_partials = nullptr;     // reduction partials, 4 banks
+  size_t partials_per_bank = 0;
+  dwa::DevScalars* d_scal = nullptr;
+  dwa::DevScalars* h_scal = nullptr;  // pinned
+  double* d_red = nullptr;          // small result slots for standalone reductions
+};
+
+namespace dwa {
+
+// kernel launchers (kernels.hip)
+struct HopOp {
+  const void* in;       // SoA field of the input parity
+  void* out;            // SoA field of the output parity
+  const void* pre;      // optional, output parity: h' = hop_coef * H in + pre_coef * pre
+  const void* post;     // optional, output parity: out = M h' + post_coef * post
+  double hop_coef, pre_coef, post_coef;
+  int mix;              // MixKind applied to h' (MIX_IDENTITY = none)
+  int parity_out;
+  int nslices;          // number of 5D slices (Ls, or n for plain D_w)
+  double* partials;     // optional per-block |out|^2 partial sums
+};
+
+int launch_hop(dwa_ctx* ctx, int prec, const HopOp& op, int* nblocks_out);
+int launch_smix(dwa_ctx* ctx, int prec, int mix, void* out, const void* in, const void* post,
+                double post_coef, int nslices, double* partials, int* nblocks_out);
+int launch_pack_links(dwa_ctx* ctx, int prec, void* dst, const void* src_canon);
+int launch_pack5(dwa_ctx* ctx, int prec, void* dst_soa, const void* src_canon, int parity,
+                 int nslices);
+int launch_unpack5(dwa_ctx* ctx, int prec, void* dst_canon, const void* src_soa, int parity,
+                   int nslices);
+int launch_convert(dwa_ctx* ctx, int prec_out, void* out, int prec_in, const void* in, size_t n,
+                   double scale);
+int launch_zero(dwa_ctx* ctx, int prec, void* p, size_t n);
+int launch_axpby(dwa_ctx* ctx, int prec, void* y, double a, const void* x, double b, size_t n);
+int launch_norm2(dwa_ctx* ctx, int prec, const void* x, size_t n, double* partials, int* nblocks);
+int launch_sum_partials(dwa_ctx* ctx, const double* partials, int n, double* out);
+int launch_source(dwa_ctx* ctx, void* chi_b, void* chi_r, void* aux_b, void* aux_r, const void* eta);
+int launch_extract(dwa_ctx* ctx, void* y1, const void* psi_b, const void* psi_r);
+int launch_check_finite(dwa_ctx* ctx, const void* canon, size_t ncomplex, int* d_flag);
+
+// CGLS building blocks (templated on precision inside kernels.hip)
+int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
+                      const void* q, const DevScalars* s, double* partials, int* nblocks);
+int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
+                      const DevScalars* s);
+int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* partials_a, int na,
+                       const double* partials_b, int nb);
+
+size_t field_elems(const dwa_ctx* ctx);  // Ls * 12 * Vh complex numbers
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+}  // namespace dwa

@@ -1,0 +1,281 @@
+"""ctypes binding of libdwa (include/dwa.h).
+
+Argument marshalling only: every arithmetic step runs in the HIP library.  Device
+memory and streams come from PyTorch; fields are passed as ``tensor.data_ptr()``.
+If ``libdwa.so`` has not been built this module raises on first use; there is no
+fallback path.
+
+Tensor shapes used by the wrappers:
+  links            complex128 (4, V, 3, 3)
+  4D field         complex128 (V, 4, 3)
+  5D field         complex128 (Ls, V, 4, 3)
+  half field F64   complex128 (Ls, 12, Vh)
+  half field F32   complex64  (Ls, 12, Vh)
+  half field BF16  bfloat16   (Ls, 12, Vh, 2)   (re, im)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_size_t, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdwa.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "dwa.h")
+
+DWA_OK, DWA_EINVAL, DWA_ENOMEM, DWA_EHIP, DWA_ENOCONV, DWA_EBREAKDOWN, DWA_ENAN, DWA_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+DWA_F64, DWA_F32, DWA_BF16 = 0, 1, 2
+PREC = {"f64": DWA_F64, "f32": DWA_F32, "bf16": DWA_BF16}
+
+MIX_KINDS = {"identity": 0, "BG": 1, "N": 2, "Ginv_Iinv": 3, "g5_IinvT_Ginv": 4, "NT": 5,
+             "G_BT_g5": 6, "Iinv": 7, "I_alpha": 8}
+
+
+class dwa_params(ctypes.Structure):
+    _fields_ = [("dims", c_int * 4), ("Ls", c_int), ("M5", c_double), ("m", c_double),
+                ("alpha", c_double), ("b", POINTER(c_double)), ("c", POINTER(c_double)),
+                ("antiperiodic_t", c_int)]
+
+
+class dwa_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", c_double), ("maxiter", c_int), ("inner_prec", c_int), ("delta", c_double),
+                ("check_every", c_int), ("warm_start", c_int)]
+
+
+class dwa_solve_stats(ctypes.Structure):
+    _fields_ = [("iters", c_int), ("outer", c_int), ("converged", c_int), ("rel_resid", c_double),
+                ("time_ms", c_double), ("n_Dbb", c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DwaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libdwa status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libdwa.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1501_04950_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sig = {
+        "dwa_create": (c_int, [POINTER(c_void_p), POINTER(dwa_params), P]),
+        "dwa_destroy": (c_int, [P]),
+        "dwa_set_links": (c_int, [P, P]),
+        "dwa_field_bytes": (c_size_t, [P, c_int]),
+        "dwa_get_sizes": (c_int, [P, POINTER(c_longlong), POINTER(c_int)]),
+        "dwa_pack_spinor5": (c_int, [P, c_int, P, P, c_int]),
+        "dwa_unpack_spinor5": (c_int, [P, c_int, P, P, c_int]),
+        "dwa_apply_Dw": (c_int, [P, P, P, c_int]),
+        "dwa_apply_Dbb": (c_int, [P, c_int, P, P]),
+        "dwa_apply_Dbb_dag": (c_int, [P, c_int, P, P]),
+        "dwa_cgne_solve": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats)]),
+        "dwa_propagator": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats), P]),
+        "dwa_strerror": (ctypes.c_char_p, [c_int]),
+        "dwa_last_error": (ctypes.c_char_p, []),
+        "dwa_debug_smatrix": (c_int, [POINTER(dwa_params), c_int, POINTER(c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions declared in include/dwa.h."""
+    txt = open(HEADER_PATH).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dwa_[a-z0-9_A-Z]+)\s*\(", txt)))
+
+
+def _raise(rc):
+    L = lib()
+    raise DwaError(rc, f"{L.dwa_strerror(rc).decode()} ({L.dwa_last_error().decode()})")
+
+
+def check(rc, allow=()):
+    if rc != DWA_OK and rc not in allow:
+        _raise(rc)
+    return rc
+
+
+def make_params(dims, Ls, M5, m, alpha, b, c, antiperiodic_t=True):
+    bb = np.ascontiguousarray(np.broadcast_to(np.asarray(b, dtype=np.float64), (Ls,)))
+    cc = np.ascontiguousarray(np.broadcast_to(np.asarray(c, dtype=np.float64), (Ls,)))
+    p = dwa_params()
+    p.dims = (c_int * 4)(*[int(d) for d in dims])
+    p.Ls, p.M5, p.m, p.alpha = int(Ls), float(M5), float(m), float(alpha)
+    p.b = bb.ctypes.data_as(POINTER(c_double))
+    p.c = cc.ctypes.data_as(POINTER(c_double))
+    p.antiperiodic_t = 1 if antiperiodic_t else 0
+    p._keep = (bb, cc)
+    return p
+
+
+def dwa_debug_smatrix(dims, Ls, M5, m, alpha, b, c, kind):
+    """Host-only: the [2][Ls][Ls] fifth-dimension matrix of the given kind."""
+    p = make_params(dims, Ls, M5, m, alpha, b, c)
+    out = np.zeros((2, Ls, Ls), dtype=np.float64)
+    k = MIX_KINDS[kind] if isinstance(kind, str) else int(kind)
+    check(lib().dwa_debug_smatrix(byref(p), k, out.ctypes.data_as(POINTER(c_double))))
+    return out
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr())
+
+
+class Context:
+    """One lattice, parameter set and gauge field on the current GPU (dwa_create)."""
+
+    def __init__(self, dims, Ls, M5, m, alpha, b, c, antiperiodic_t=True, stream=None):
+        torch = _torch()
+        self.dims, self.Ls = tuple(int(d) for d in dims), int(Ls)
+        self.V = int(np.prod(self.dims))
+        self.Vh = self.V // 2
+        self.params = make_params(dims, Ls, M5, m, alpha, b, c, antiperiodic_t)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._h = c_void_p()
+        check(lib().dwa_create(byref(self._h), byref(self.params), c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if self._h:
+            lib().dwa_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- fields -------------------------------------------------------------
+    def half_field(self, prec="f64", zero=True):
+        torch = _torch()
+        p = PREC[prec] if isinstance(prec, str) else prec
+        shape = (self.Ls, 12, self.Vh)
+        f = torch.zeros if zero else torch.empty
+        if p == DWA_F64:
+            return f(shape, dtype=torch.complex128, device=self.device)
+        if p == DWA_F32:
+            return f(shape, dtype=torch.complex64, device=self.device)
+        return f(shape + (2,), dtype=torch.bfloat16, device=self.device)
+
+    def _check_half(self, t, prec):
+        torch = _torch()
+        p = PREC[prec] if isinstance(prec, str) else prec
+        want = {DWA_F64: torch.complex128, DWA_F32: torch.complex64, DWA_BF16: torch.bfloat16}[p]
+        n = self.Ls * 12 * self.Vh * (2 if p == DWA_BF16 else 1)
+        if t.dtype != want or not t.is_contiguous() or t.numel() != n or t.device != self.device:
+            raise ValueError(f"half field must be a contiguous {want} tensor of {n} elements on {self.device}")
+        return p
+
+    def _check_canon(self, t, shape):
+        torch = _torch()
+        if (t.dtype != torch.complex128 or not t.is_contiguous() or tuple(t.shape) != tuple(shape)
+                or t.device != self.device):
+            raise ValueError(f"expected contiguous complex128 {tuple(shape)} on {self.device}")
+
+    def set_links(self, U):
+        self._check_canon(U, (4, self.V, 3, 3))
+        check(lib().dwa_set_links(self._h, _ptr(U)))
+
+    def pack(self, canon5, parity, prec="f64"):
+        self._check_canon(canon5, (self.Ls, self.V, 4, 3))
+        out = self.half_field(prec, zero=False)
+        p = self._check_half(out, prec)
+        check(lib().dwa_pack_spinor5(self._h, p, _ptr(out), _ptr(canon5), int(parity)))
+        return out
+
+    def unpack(self, half, parity, prec="f64", out=None):
+        torch = _torch()
+        p = self._check_half(half, prec)
+        if out is None:
+            out = torch.zeros((self.Ls, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        self._check_canon(out, (self.Ls, self.V, 4, 3))
+        check(lib().dwa_unpack_spinor5(self._h, p, _ptr(out), _ptr(half), int(parity)))
+        return out
+
+    # -- operators ------------------------------------------------------------
+    def apply_Dw(self, inp):
+        torch = _torch()
+        n = inp.shape[0]
+        self._check_canon(inp, (n, self.V, 4, 3))
+        out = torch.empty_like(inp)
+        check(lib().dwa_apply_Dw(self._h, _ptr(out), _ptr(inp), int(n)))
+        return out
+
+    def apply_Dbb(self, inp, prec="f64", out=None, dagger=False):
+        p = self._check_half(inp, prec)
+        if out is None:
+            out = self.half_field(prec, zero=False)
+        self._check_half(out, prec)
+        fn = lib().dwa_apply_Dbb_dag if dagger else lib().dwa_apply_Dbb
+        check(fn(self._h, p, _ptr(out), _ptr(inp)))
+        return out
+
+    def apply_Dbb_dag(self, inp, prec="f64", out=None):
+        return self.apply_Dbb(inp, prec, out, dagger=True)
+
+    # -- solvers --------------------------------------------------------------
+    @staticmethod
+    def opts(tol=1e-10, maxiter=100000, inner_prec="f64", delta=0.1, check_every=1,
+             warm_start=False):
+        o = dwa_solve_opts()
+        o.tol, o.maxiter = float(tol), int(maxiter)
+        o.inner_prec = PREC[inner_prec] if isinstance(inner_prec, str) else int(inner_prec)
+        o.delta, o.check_every, o.warm_start = float(delta), int(check_every), int(bool(warm_start))
+        return o
+
+    def cgne_solve(self, rhs, x=None, **kw):
+        """Returns (x, stats dict, status)."""
+        self._check_half(rhs, "f64")
+        if x is None:
+            x = self.half_field("f64")
+        self._check_half(x, "f64")
+        o = self.opts(**kw)
+        st = dwa_solve_stats()
+        rc = check(lib().dwa_cgne_solve(self._h, _ptr(x), _ptr(rhs), byref(o), byref(st)),
+                   allow=(DWA_ENOCONV,))
+        return x, st.as_dict(), rc
+
+    def propagator(self, eta, want_psi=False, **kw):
+        """Returns (y1, stats dict, status[, psi5])."""
+        torch = _torch()
+        self._check_canon(eta, (self.V, 4, 3))
+        y1 = torch.zeros((self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        psi = None
+        if want_psi:
+            psi = torch.zeros((self.Ls, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        o = self.opts(**kw)
+        st = dwa_solve_stats()
+        rc = check(lib().dwa_propagator(self._h, _ptr(y1), _ptr(eta), byref(o), byref(st),
+                                        _ptr(psi) if psi is not None else None),
+                   allow=(DWA_ENOCONV,))
+        if want_psi:
+            return y1, st.as_dict(), rc, psi
+        return y1, st.as_dict(), rc

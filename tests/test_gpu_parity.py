@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the
+same seeded inputs.
+
+FP64 operators must agree with the oracle to 1e-12 relative (they agree to
+rounding, ~1e-15).  FP32 and BF16 storage state their error against the FP64
+oracle.  Solves are compared through their residuals and the kappa * tol bound.
+"""
+
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import redblack, wilson
+from paper_1501_04950_amd import dwa, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: dims, Ls, M5, m, alpha, b, c  (b, c None -> per-slice random)
+    "tiny_2x2x2x2_ls4": ((2, 2, 2, 2), 4, -1.8, 0.1, 0.7, None, None),
+    "ragged_2x2x2x6_ls2": ((2, 2, 2, 6), 2, -1.7, 0.2, 1.3, None, None),
+    "c1_4x4x4x4_ls8": ((4, 4, 4, 4), 8, -1.8, 0.05, 0.8, 1.5, 0.5),
+    "lsmax32_4x2x2x4_ls20": ((4, 2, 2, 4), 20, -1.6, 0.03, 0.9, None, None),
+    "c2_8x8x8x16_ls12": ((8, 8, 8, 16), 12, -1.8, 0.02, 0.6, 1.5, 0.5),
+}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+class Case:
+    def __init__(self, name):
+        dims, Ls, M5, m, alpha, b, c = CASES[name]
+        rng = np.random.default_rng(zlib.crc32(name.encode()))
+        self.b = np.full(Ls, b) if b is not None else rng.uniform(1.0, 2.0, Ls)
+        self.c = np.full(Ls, c) if c is not None else rng.uniform(0.1, 0.9, Ls)
+        self.name, self.dims, self.Ls, self.M5, self.m, self.alpha = name, dims, Ls, M5, m, alpha
+        self.U = synth.su3_field(dims, 0.5, 7 + Ls)
+        self.p = redblack.Params.make(dims, Ls, M5, m, alpha, self.b, self.c)
+        self.rb = None
+
+    def oracle(self):
+        if self.rb is None:
+            self.rb = redblack.RedBlack(self.U, self.p)
+        return self.rb
+
+    def ctx(self, alpha=None):
+        dev = gpu()
+        say(f"[gpu] create context {self.name} alpha={alpha or self.alpha}")
+        ctx = dwa.Context(self.dims, self.Ls, self.M5, self.m, alpha or self.alpha, self.b, self.c)
+        ctx.set_links(torch.from_numpy(self.U).to(dev))
+        return ctx
+
+    def black_field(self, seed):
+        f = synth.gaussian_field5(self.dims, self.Ls, seed)
+        return f * self.oracle().black
+
+
+_cases = {}
+
+
+def case(name):
+    if name not in _cases:
+        _cases[name] = Case(name)
+    return _cases[name]
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 0.0), ("f32", 1e-7), ("bf16", 5e-3)])
+def test_pack_roundtrip(prec, tol):
+    cs = case("ragged_2x2x2x6_ls2")
+    ctx = cs.ctx()
+    f = synth.gaussian_field5(cs.dims, cs.Ls, 3)
+    ft = torch.from_numpy(f).to(gpu())
+    say(f"[gpu] pack/unpack {prec}")
+    out = torch.zeros_like(ft)
+    for par in (0, 1):
+        half = ctx.pack(ft, par, prec)
+        ctx.unpack(half, par, prec, out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    if tol == 0.0:
+        assert np.array_equal(got, f)
+    else:
+        assert np.abs(got - f).max() <= tol * np.abs(f).max() * 2
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["tiny_2x2x2x2_ls4", "ragged_2x2x2x6_ls2", "c1_4x4x4x4_ls8"])
+def test_dw_matches_oracle(name):
+    cs = case(name)
+    ctx = cs.ctx()
+    n = 3
+    f = synth.gaussian_source(cs.dims, 5, leading=(n,))
+    say(f"[gpu] apply_Dw {name} n={n}")
+    out = ctx.apply_Dw(torch.from_numpy(f).to(gpu())).cpu().numpy()
+    ref = wilson.dw(cs.U, f, cs.M5, cs.dims)
+    assert rel(out, ref) < 1e-13
+    ctx.close()
+
+
+def _gpu_dbb(cs, ctx, x_full, prec="f64", dagger=False):
+    xt = torch.from_numpy(np.ascontiguousarray(x_full)).to(gpu())
+    half = ctx.pack(xt, 0, prec)
+    say(f"[gpu] apply_Dbb{'_dag' if dagger else ''} {cs.name} {prec}")
+    out = ctx.apply_Dbb(half, prec, dagger=dagger)
+    full = torch.zeros_like(xt)
+    ctx.unpack(out, 0, prec, out=full)
+    return full.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dbb_matches_oracle(name):
+    cs = case(name)
+    ctx = cs.ctx()
+    x = cs.black_field(11)
+    got = _gpu_dbb(cs, ctx, x)
+    ref = cs.oracle().Dbb(x)
+    r = rel(got, ref)
+    say(f"    D_bb rel err {r:.2e}")
+    assert r < 1e-13
+    got_d = _gpu_dbb(cs, ctx, x, dagger=True)
+    ref_d = cs.oracle().Dbb_dag(x)
+    rd = rel(got_d, ref_d)
+    say(f"    D_bb^dag rel err {rd:.2e}")
+    assert rd < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 2e-2)])
+def test_dbb_low_precision_error(prec, bound):
+    cs = case("c1_4x4x4x4_ls8")
+    ctx = cs.ctx()
+    x = cs.black_field(12)
+    ref = cs.oracle().Dbb(x)
+    got = _gpu_dbb(cs, ctx, x, prec)
+    r = rel(got, ref)
+    say(f"    D_bb {prec} rel err vs FP64 oracle {r:.2e}")
+    assert r < bound
+    ctx.close()
+
+
+def test_cgne_matches_oracle_cgls():
+    """Same CGLS, same stopping rule: iteration counts agree within one and the
+    solutions agree to the accuracy both residuals allow."""
+    cs = case("c1_4x4x4x4_ls8")
+    rb = cs.oracle()
+    rhs = cs.black_field(13)
+    x_ref, info = redblack.cgls(rb.Dbb, rb.Dbb_dag, rhs, 1e-10, 2000)
+    ctx = cs.ctx()
+    say("[gpu] cgne_solve c1 f64")
+    half = ctx.pack(torch.from_numpy(rhs).to(gpu()), 0, "f64")
+    x, st, rc = ctx.cgne_solve(half, tol=1e-10, maxiter=2000, check_every=1)
+    assert rc == dwa.DWA_OK and st["converged"]
+    full = torch.zeros((cs.Ls,) + rhs.shape[1:], dtype=torch.complex128, device=gpu())
+    ctx.unpack(x, 0, "f64", out=full)
+    xg = full.cpu().numpy()
+    say(f"    iters gpu {st['iters']} oracle {info.iters}; true resid gpu {st['rel_resid']:.2e}; "
+        f"x diff {rel(xg, x_ref):.2e}")
+    assert abs(st["iters"] - info.iters) <= 1
+    assert st["rel_resid"] <= 1.5e-10
+    assert rel(rb.Dbb(xg), rhs) <= 1.5e-10
+    assert rel(xg, x_ref) < 1e-8
+    ctx.close()
+
+
+def test_propagator_matches_oracle():
+    """y_1 for a point source (site 0, spin 0, colour 0) on the 4^4, Ls=8 lattice."""
+    cs = case("c1_4x4x4x4_ls8")
+    eta = synth.point_source(cs.dims, 0, 0, 0)
+    y_ref, info = redblack.propagator(cs.U, eta, cs.p, tol=1e-12)
+    ctx = cs.ctx()
+    say("[gpu] propagator c1 f64 tol 1e-12")
+    y, st, rc = ctx.propagator(torch.from_numpy(eta).to(gpu()), tol=1e-12, check_every=1)
+    yg = y.cpu().numpy()
+    r = rel(yg, y_ref)
+    say(f"    y1 rel diff {r:.2e} iters gpu {st['iters']} oracle {info.iters}")
+    assert rc == dwa.DWA_OK
+    assert abs(st["iters"] - info.iters) <= 1
+    assert r < 1e-10
+    ctx.close()
+
+
+def test_propagator_psi_solves_full_system():
+    """The returned 5D psi satisfies D_alpha psi = D_1(1) P b (oracle's literal operators)."""
+    cs = case("tiny_2x2x2x2_ls4")
+    eta = synth.gaussian_source(cs.dims, 21)
+    ctx = cs.ctx()
+    say("[gpu] propagator tiny with psi")
+    y, st, rc, psi = ctx.propagator(torch.from_numpy(eta).to(gpu()), want_psi=True, tol=1e-13)
+    psi = psi.cpu().numpy()
+    rho = redblack.source_rhs(cs.U, eta, cs.p)
+    assert rel(cs.oracle().D(psi), rho) < 1e-11
+    assert rel(y.cpu().numpy(), redblack.extract_y1(psi)) < 1e-15
+    ctx.close()
+
+
+def test_y1_alpha_independent_on_gpu():
+    cs = case("c1_4x4x4x4_ls8")
+    eta = torch.from_numpy(synth.gaussian_source(cs.dims, 22)).to(gpu())
+    ys = []
+    for alpha in (0.6, 1.0, 1.3):
+        ctx = cs.ctx(alpha)
+        say(f"[gpu] propagator alpha={alpha}")
+        y, st, rc = ctx.propagator(eta, tol=1e-12, check_every=10)
+        assert rc == dwa.DWA_OK
+        ys.append(y.cpu().numpy())
+        ctx.close()
+    assert rel(ys[0], ys[1]) < 1e-9 and rel(ys[2], ys[1]) < 1e-9
+
+
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_mixed_precision_reaches_fp64_accuracy(inner):
+    cs = case("c1_4x4x4x4_ls8")
+    eta = torch.from_numpy(synth.point_source(cs.dims, 0, 1, 2)).to(gpu())
+    ctx = cs.ctx()
+    say(f"[gpu] propagator f64 reference")
+    y64, st64, rc = ctx.propagator(eta, tol=1e-10, check_every=5)
+    say(f"[gpu] propagator mixed {inner}")
+    y, st, rc = ctx.propagator(eta, tol=1e-10, inner_prec=inner, delta=0.1 if inner == "f32" else 0.3,
+                               check_every=5)
+    say(f"    {inner}: iters {st['iters']} outer {st['outer']} resid {st['rel_resid']:.2e}; "
+        f"f64 iters {st64['iters']}")
+    assert rc == dwa.DWA_OK and st["rel_resid"] <= 1e-10
+    assert rel(y.cpu().numpy(), y64.cpu().numpy()) < 1e-8
+    ctx.close()
+
+
+def test_error_paths():
+    cs = case("tiny_2x2x2x2_ls4")
+    dev = gpu()
+    ctx = dwa.Context(cs.dims, cs.Ls, cs.M5, cs.m, cs.alpha, cs.b, cs.c)
+    say("[gpu] error paths")
+    half = ctx.half_field("f64")
+    with pytest.raises(dwa.DwaError) as e:
+        ctx.apply_Dbb(half)
+    assert e.value.status == dwa.DWA_ESTATE
+    ctx.set_links(torch.from_numpy(cs.U).to(dev))
+    eta = synth.gaussian_source(cs.dims, 3)
+    eta[5, 1, 2] = np.nan
+    with pytest.raises(dwa.DwaError) as e:
+        ctx.propagator(torch.from_numpy(eta).to(dev))
+    assert e.value.status == dwa.DWA_ENAN
+    eta = torch.from_numpy(synth.gaussian_source(cs.dims, 4)).to(dev)
+    y, st, rc = ctx.propagator(eta, tol=1e-14, maxiter=2)
+    assert rc == dwa.DWA_ENOCONV and st["iters"] == 2 and not st["converged"]
+    ctx.close()
