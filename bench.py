@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the alpha-Moebius domain-wall propagator on one MI355X.
+
+Workload (the paper-shaped configuration): 16^3 x 32 lattice, Ls = 16, seeded
+SU(3) links of spread 0.7 after two APE-like smearing steps (coefficient 0.5),
+M5 = -1.8 (Wilson diagonal 2.2), m = 0.01, b = 1.5, c = 0.5, Z2-noise source.
+
+One step is one full pass of the hot path: source rho = D_1(1) P b, Schur
+right-hand side, CG on the normal equations of D_bb to a 1e-10 relative residual
+(mixed precision: inner CGLS with low-precision storage, FP64 defect correction),
+reconstruction and extraction of y_1.  Inputs are resident in HBM before the timed
+region.  The JSON line reports the mixed-precision time to 1e-10 as `value`, the
+FP64 time beside it, D_bb bandwidth per precision, the roofline of the fused hop
+kernel (HIP events on the library's stream), and the CPU oracle on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+METRIC = "CGNE time-to-1e-10 + D_bb HBM GB/s, mixed vs FP64, 16^3x32 L_s=16"
+HBM_PEAK_GBS = 8000.0
+FLOPS_PER_SITE_DW = 1320
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3_16x16x16x32_ls16")
+    ap.add_argument("--inner", default="bf16", choices=["f32", "bf16"])
+    ap.add_argument("--delta", type=float, default=None)
+    ap.add_argument("--alpha", type=float, default=1.0)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 512 MiB device copy (scale reference for HBM counters)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): a solve is not "
+              "split across GPUs in this library", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1501_04950_amd import dwa, synth
+
+    w = synth.WORKLOADS[args.workload]
+    dims, Ls = w["dims"], w["Ls"]
+    V = int(np.prod(dims))
+    Vh = V // 2
+    log(f"generating links {dims} Ls={Ls}")
+    U = synth.workload_links(args.workload)
+    plaq = synth.plaquette(U, dims)
+    eta = synth.z2_source(dims, w["seed"] + 100)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    ctx = dwa.Context(dims, Ls, w["M5"], w["m"], args.alpha, w["b"], w["c"])
+    Ud = torch.from_numpy(U).to(dev)
+    ctx.set_links(Ud)
+    eta_d = torch.from_numpy(eta).to(dev)
+    torch.cuda.synchronize()
+
+    eb = {"f64": 16, "f32": 8, "bf16": 4}
+    S = {p: Ls * 12 * Vh * eb[p] for p in eb}
+    L = {p: 4 * V * 9 * eb[p] for p in eb}
+
+    def ev_time(fn, reps):
+        """Average milliseconds of fn() over reps, HIP events on the library stream."""
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for i in range(reps):
+            fn(i)
+        end.record(stream)
+        end.synchronize()
+        return start.elapsed_time(end) / reps
+
+    # --- kernel and operator bandwidth (rotating buffers, > 512 MiB per set) ------
+    kern = {}
+    for prec in ("f64", "f32", "bf16"):
+        nset = max(2, int(np.ceil(600e6 / (2 * S[prec]))))
+        ins = [ctx.half_field(prec) for _ in range(nset)]
+        for t in ins:
+            if prec == "bf16":
+                t.copy_(torch.randn(t.shape, device=dev).to(torch.bfloat16))
+            else:
+                t.copy_(torch.randn(t.shape, dtype=t.dtype, device=dev))
+        outs = [ctx.half_field(prec) for _ in range(nset)]
+        reds = [ctx.half_field(prec) for _ in range(nset)]
+        log(f"timing {prec}: {nset} buffer sets")
+        for i in range(3):
+            ctx.apply_hop(ins[i % nset], 1, "N", prec, out=reds[i % nset])
+        hop_ms = ev_time(lambda i: ctx.apply_hop(ins[i % nset], 1, "N", prec, out=reds[i % nset]),
+                         args.kernel_reps)
+        dbb_ms = ev_time(lambda i: ctx.apply_Dbb(ins[i % nset], prec, out=outs[i % nset]),
+                         args.kernel_reps)
+        dag_ms = ev_time(lambda i: ctx.apply_Dbb_dag(ins[i % nset], prec, out=outs[i % nset]),
+                         args.kernel_reps)
+        hop_bytes = 2 * S[prec] + L[prec]
+        dbb_bytes = 5 * S[prec] + 2 * L[prec]
+        kern[prec] = {
+            "hop_us": hop_ms * 1e3, "hop_gbs": hop_bytes / hop_ms / 1e6,
+            "dbb_us": dbb_ms * 1e3, "dbb_gbs": dbb_bytes / dbb_ms / 1e6,
+            "dbb_dag_us": dag_ms * 1e3, "dbb_dag_gbs": dbb_bytes / dag_ms / 1e6,
+            "dbb_gflops": FLOPS_PER_SITE_DW * V * Ls / dbb_ms / 1e6,
+        }
+        log(f"  {prec}: hop {kern[prec]['hop_us']:.1f} us {kern[prec]['hop_gbs']:.0f} GB/s | "
+            f"D_bb {kern[prec]['dbb_us']:.1f} us {kern[prec]['dbb_gbs']:.0f} GB/s")
+        del ins, outs, reds
+        torch.cuda.empty_cache()
+
+    if args.copy_probe:
+        a = torch.empty(512 * 2**20 // 4, dtype=torch.float32, device=dev).normal_()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # --- FP64 reference solve ---------------------------------------------------------
+    fp64 = None
+    y64 = None
+    if not args.no_fp64:
+        log("FP64 propagator solve")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y64, st64, rc = ctx.propagator(eta_d, tol=args.tol, inner_prec="f64",
+                                       check_every=args.check_every)
+        torch.cuda.synchronize()
+        fp64 = {"time_s": time.perf_counter() - t0, "iters": st64["iters"],
+                "rel_resid": st64["rel_resid"], "status": rc}
+        log(f"  FP64: {fp64['time_s']:.3f} s, {st64['iters']} iters, resid {st64['rel_resid']:.2e}")
+
+    # --- mixed-precision steps (timed) ------------------------------------------------
+    delta = args.delta if args.delta is not None else (0.3 if args.inner == "bf16" else 0.05)
+    kw = dict(tol=args.tol, inner_prec=args.inner, delta=delta, check_every=args.check_every)
+    for i in range(args.warmup):
+        log(f"warmup {i}")
+        ctx.propagator(eta_d, **kw)
+    torch.cuda.synchronize()
+    times, stats = [], []
+    y = None
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y, st, rc = ctx.propagator(eta_d, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        stats.append(st)
+        log(f"step {i}: {times[-1]:.3f} s, iters {st['iters']} outer {st['outer']} "
+            f"resid {st['rel_resid']:.2e} status {rc}")
+    mixed_s = statistics.mean(times)
+    y_err = None
+    if y64 is not None:
+        y_err = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
+
+    # --- CPU oracle on a bounded sample ---------------------------------------------
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(U, dims, Ls, w, args.alpha, fp64)
+
+    dom = kern[args.inner]
+    roofline = {
+        "bound": "hbm",
+        "kernel": f"hop_mix_kernel<{args.inner.upper()},16,16,0> (fused Wilson hop + N mix)",
+        "achieved": round(dom["hop_gbs"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(dom["hop_gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "bytes_per_launch": 2 * S[args.inner] + L[args.inner],
+    }
+    result = {
+        "metric": METRIC,
+        "value": round(mixed_s, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed_s * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{args.inner} storage, f32 arithmetic; f64 outer",
+        "data": "synthetic",
+        "config": {"workload": f"{dims[0]}^3x{dims[3]} Ls={Ls} m={w['m']} alpha={args.alpha} "
+                               f"M5={w['M5']} b={w['b']} c={w['c']} Z2 source, tol {args.tol}",
+                   "plaquette": round(plaq, 6), "inner": args.inner, "delta": delta},
+        "mixed": {"time_s": round(mixed_s, 4), "iters": stats[-1]["iters"],
+                  "outer": stats[-1]["outer"], "rel_resid": stats[-1]["rel_resid"],
+                  "y1_rel_diff_vs_fp64": y_err},
+        "fp64": fp64,
+        "speedup_mixed_vs_fp64": round(fp64["time_s"] / mixed_s, 3) if fp64 else None,
+        "dbb": {p: {k: round(v, 2) for k, v in kern[p].items()} for p in kern},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(result), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(U, dims, Ls, w, alpha, fp64):
+    """The oracle as it stands, timed on this host: one application of its D_bb on the
+    same workload, scaled to a CGNE solve by the FP64 iteration count (each CGLS
+    iteration applies D_bb and D_bb^dag once)."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import redblack
+    from paper_1501_04950_amd import synth
+
+    log("CPU oracle: one D_bb application on the full workload")
+    p = redblack.Params.make(dims, Ls, w["M5"], w["m"], alpha, w["b"], w["c"])
+    rb = redblack.RedBlack(U, p)
+    x = synth.gaussian_field5(dims, Ls, 5) * rb.black
+    c0, t0 = time.process_time(), time.perf_counter()
+    rb.Dbb(x)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    iters = fp64["iters"] if fp64 else None
+    est = wall * 2 * iters if iters else None
+    return {"value": round(est, 1) if est else None, "unit": "s",
+            "cores": max(1, round(cpu / wall)),
+            "host_cores_available": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
+            "sample": f"one oracle D_bb on the 16^3x32 Ls=16 workload took {wall:.1f} s; "
+                      f"scaled by 2 x {iters} FP64 CGLS iterations"}
+
+
+if __name__ == "__main__":
+    main()

@@ -147,6 +147,14 @@ int dwa_apply_Dw(dwa_ctx *ctx, void *out, const void *in, int nslices);
 int dwa_apply_Dbb(dwa_ctx *ctx, int prec, void *out_b, const void *in_b);
 int dwa_apply_Dbb_dag(dwa_ctx *ctx, int prec, void *out_b, const void *in_b);
 
+/* One launch of the fused hop kernel: out = M_kind (H in), where H is the hopping sum
+ * of eq.(wilson) without its -1/2, taken from the parity 1 - parity_out to parity_out
+ * on every slice, and M_kind is a fifth-dimension matrix of dwa_debug_smatrix (kinds
+ * 0..6; 0 = identity runs the hop alone).  D_bb is built from two such launches
+ * (kinds 2 and 3) and D_bb^dag from kinds 5 and 6.  Half fields of precision prec;
+ * out and in must not overlap.  Exposed for measurement and tests. */
+int dwa_apply_hop(dwa_ctx *ctx, int prec, int parity_out, int kind, void *out, const void *in);
+
 /* Solve D_bb x_b = rhs_b by CG on the normal equations (Sec. 3).  x_b and rhs_b are
  * FP64 black SoA fields.  Returns DWA_OK, DWA_ENOCONV (x_b holds the last iterate) or
  * DWA_EBREAKDOWN.  stats may be NULL. */

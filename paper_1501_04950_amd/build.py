@@ -2,31 +2,51 @@
 
     python -m paper_1501_04950_amd.build
 
-Every source is compiled for gfx950 only, with packed FP32 instructions turned
-off in device code.
+Each source is compiled to an object in parallel (one translation unit per field
+precision carries most of the kernels), then linked into one shared library.  Device
+code targets gfx950 only, with packed FP32 instructions turned off.
 """
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = ["csrc/kernels.hip", "csrc/api.cpp", "csrc/smat.cpp"]
+SOURCES = ["csrc/kernels_f64.hip", "csrc/kernels_f32.hip", "csrc/kernels_bf16.hip",
+           "csrc/kernels.hip", "csrc/api.cpp", "csrc/smat.cpp"]
 LIB = os.path.join(PKG, "libdwa.so")
+OBJDIR = os.path.join(PKG, "_build")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I", os.path.join(ROOT, "include")]
 
 
-def hipcc_cmd(out=LIB):
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    return ([hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-I", os.path.join(ROOT, "include"), "-x", "hip"]
-            + [os.path.join(PKG, s) for s in SOURCES] + ["-o", out])
+def _compile(src, verbose):
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(PKG, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    msgs = [l for l in (r.stdout + r.stderr).splitlines()
+            if "packed-fp32-ops' is not a recognized feature" not in l and l.strip()]
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n" + "\n".join(msgs))
+    return obj, msgs
 
 
-def build(verbose=True):
+def build(verbose=True, jobs=None):
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    for _, msgs in results:
+        for m in msgs:
+            print(m, flush=True)
     tmp = LIB + ".tmp"
-    cmd = hipcc_cmd(tmp)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for o, _ in results] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

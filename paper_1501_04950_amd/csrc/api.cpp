@@ -2,8 +2,10 @@
 // propagator pipeline.  Host code; every arithmetic step runs in kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -334,7 +336,9 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
   if ((long long)p->Ls * 12 * V > (1LL << 31) - 1) return einval("field too large for 32-bit indexing");
   std::vector<double> mix;
   std::string err;
-  if (!build_smatrices(p->Ls, p->M5, p->m, p->alpha, p->b, p->c, mix, err)) return einval(err);
+  SweepTables sweeps;
+  if (!build_smatrices(p->Ls, p->M5, p->m, p->alpha, p->b, p->c, mix, err, &sweeps))
+    return einval(err);
 
   dwa_ctx* ctx = new dwa_ctx();
   for (int d = 0; d < 4; ++d) ctx->dims[d] = p->dims[d];
@@ -396,6 +400,38 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
   if ((rc = hip_fail(hipMemcpy(ctx->d_nbr, nbr.data(), sizeof(int) * nbr.size(),
                                hipMemcpyHostToDevice), "upload nbr")))
     return fail(rc);
+  // fused-hop traversal: chunks of NS consecutive checkerboard sites, ordered by
+  // (t-slab, z, t within the slab, y, x) so that a run of blocks on one XCD touches a
+  // compact slab and the t and z neighbours are re-read from L2, not HBM.  Contiguous
+  // ranges of this order go to one XCD (the kernel remaps block ids accordingly).
+  {
+    const int NS = hop_sites_per_block(p->Ls);
+    const long long nchunk = (Vh + NS - 1) / NS;
+    std::vector<int> order(nchunk);
+    for (long long c = 0; c < nchunk; ++c) order[c] = (int)c;
+    const char* env = std::getenv("DWA_HOP_ORDER");
+    const bool lexical = env && std::string(env) == "lex";
+    if (!lexical) {
+      const int ts = Lt >= 16 ? Lt / 8 : 1;
+      std::vector<long long> key(nchunk);
+      for (long long c = 0; c < nchunk; ++c) {
+        long long lex = cb2lex[c * NS];
+        long long r = lex;
+        const long long x = r % Lx; r /= Lx;
+        const long long y = r % Ly; r /= Ly;
+        const long long z = r % Lz;
+        const long long t = r / Lz;
+        key[c] = ((((t / ts) * Lz + z) * ts + (t % ts)) * Ly + y) * Lx + x;
+      }
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int b) { return key[a] < key[b]; });
+    }
+    if ((rc = hip_fail(hipMalloc(&ctx->d_blkmap, sizeof(int) * order.size()), "alloc blkmap")))
+      return fail(rc);
+    if ((rc = hip_fail(hipMemcpy(ctx->d_blkmap, order.data(), sizeof(int) * order.size(),
+                                 hipMemcpyHostToDevice), "upload blkmap")))
+      return fail(rc);
+  }
   // s-matrices
   std::vector<float> mix32(mix.begin(), mix.end());
   if ((rc = hip_fail(hipMalloc(&ctx->d_mix64, sizeof(double) * mix.size()), "alloc mix"))) return fail(rc);
@@ -404,6 +440,25 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
     return fail(rc);
   if ((rc = hip_fail(hipMemcpy(ctx->d_mix32, mix32.data(), sizeof(float) * mix32.size(), hipMemcpyHostToDevice), "upload mix32")))
     return fail(rc);
+  {
+    std::vector<float> sw32(sweeps.coef.begin(), sweeps.coef.end());
+    if ((rc = hip_fail(hipMalloc(&ctx->d_sweep_meta, sizeof(int) * sweeps.meta.size()), "alloc sweep meta")))
+      return fail(rc);
+    if ((rc = hip_fail(hipMalloc(&ctx->d_sweep64, sizeof(double) * sweeps.coef.size()), "alloc sweep64")))
+      return fail(rc);
+    if ((rc = hip_fail(hipMalloc(&ctx->d_sweep32, sizeof(float) * sw32.size()), "alloc sweep32")))
+      return fail(rc);
+    if ((rc = hip_fail(hipMemcpy(ctx->d_sweep_meta, sweeps.meta.data(), sizeof(int) * sweeps.meta.size(), hipMemcpyHostToDevice), "upload sweep meta")))
+      return fail(rc);
+    if ((rc = hip_fail(hipMemcpy(ctx->d_sweep64, sweeps.coef.data(), sizeof(double) * sweeps.coef.size(), hipMemcpyHostToDevice), "upload sweep64")))
+      return fail(rc);
+    if ((rc = hip_fail(hipMemcpy(ctx->d_sweep32, sw32.data(), sizeof(float) * sw32.size(), hipMemcpyHostToDevice), "upload sweep32")))
+      return fail(rc);
+    ctx->sweep_meta_host = sweeps.meta;
+    for (size_t k = 0; k < sweeps.meta.size(); k += 4)
+      if (sweeps.meta[k + 1] == ST_DENSE) ctx->dense_mix = true;
+    if (std::getenv("DWA_DENSE_MIX")) ctx->dense_mix = true;
+  }
   // links and workspace
   const size_t n = field_elems(ctx);
   for (int pr = 0; pr < 3; ++pr)
@@ -434,8 +489,12 @@ int dwa_destroy(dwa_ctx* ctx) {
   };
   f(ctx->d_nbr);
   f(ctx->d_cb2lex);
+  f(ctx->d_blkmap);
   f(ctx->d_mix64);
   f(ctx->d_mix32);
+  f(ctx->d_sweep_meta);
+  f(ctx->d_sweep64);
+  f(ctx->d_sweep32);
   for (auto& pr : ctx->prec) f(pr.links);
   for (auto p : ctx->w64) f(p);
   for (auto p : ctx->w32) f(p);
@@ -526,6 +585,19 @@ int dwa_apply_Dbb_dag(dwa_ctx* ctx, int prec, void* out, const void* in) {
   void** W = low_pool(ctx, prec);
   const bool p64 = prec == DWA_F64;
   return apply_dbbdag(ctx, prec, out, in, W[p64 ? W_OPB : L_OPB], W[p64 ? W_OPR : L_OPR]);
+}
+
+int dwa_apply_hop(dwa_ctx* ctx, int prec, int parity_out, int kind, void* out, const void* in) {
+  DWA_TRY(check_ctx(ctx));
+  if (!out || !in) return einval("null field");
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (parity_out != 0 && parity_out != 1) return einval("parity must be 0 or 1");
+  if (kind != MIX_IDENTITY && kind != MIX_N && kind != MIX_NT && kind != MIX_GINV_IINV &&
+      kind != MIX_G_BT_G5)
+    return einval("hop output matrix must be one of kinds 0, 2, 3, 5, 6");
+  if (out == in) return einval("out and in must not overlap");
+  HopOp h{in, out, nullptr, nullptr, 1.0, 0.0, 0.0, kind, parity_out, ctx->Ls, nullptr};
+  return launch_hop(ctx, prec, h, nullptr);
 }
 
 int dwa_cgne_solve(dwa_ctx* ctx, void* x, const void* rhs, const dwa_solve_opts* o,

@@ -127,10 +127,32 @@ enum MixKind {
   MIX_COUNT
 };
 
-// Host construction (FP64) of all site-local matrices; returns false and a
-// message when the site-local block I is singular or badly conditioned.
+// Every site-local matrix above is a product of at most three simple factors per
+// chirality, so it is applied as a short program of O(Ls) sweeps over the slices:
+enum StageType {
+  ST_SCALE = 1,   // y_s = A_s x_s
+  ST_LBI = 2,     // lower cyclic bidiagonal: y_s = A_s x_s + B_s x_{s-1}, y_0 uses B_0 x_{Ls-1}
+  ST_UBI = 3,     // upper cyclic bidiagonal: y_s = A_s x_s + B_s x_{s+1}, y_{Ls-1} uses B x_0
+  ST_LSOLVE = 4,  // solve a lower cyclic bidiagonal system (A = 1/d, B = e/d, C = f, W = w)
+  ST_USOLVE = 5,  // solve an upper cyclic bidiagonal system
+  ST_DENSE = 6    // fallback: the dense Ls x Ls matrix
+};
+constexpr int kMaxStages = 3;
+constexpr int kLsPad = 32;  // coefficient rows are padded to 32 slices
+// meta: [MIX_COUNT][2][4] = {nstages, type0, type1, type2}
+// coef: [MIX_COUNT][2][kMaxStages][4][kLsPad] rows A, B, C and W (w in W[0])
+struct SweepTables {
+  std::vector<int> meta;
+  std::vector<double> coef;
+};
+
+// Host construction (FP64) of all site-local matrices and their sweep programs (each
+// checked against its dense matrix; a program that does not reproduce it to 1e-12 is
+// replaced by ST_DENSE).  Returns false and a message when the site-local block I is
+// singular or badly conditioned.
 bool build_smatrices(int Ls, double M5, double m, double alpha, const double* b, const double* c,
-                     std::vector<double>& out /* [MIX_COUNT][2][Ls][Ls] */, std::string& err);
+                     std::vector<double>& out /* [MIX_COUNT][2][Ls][Ls] */, std::string& err,
+                     SweepTables* sweeps = nullptr);
 
 // ----------------------------------------------------------------------------
 // device-side solver scalars
@@ -177,9 +199,15 @@ struct dwa_ctx {
   // geometry
   int* d_nbr = nullptr;   // [2][8][Vh] neighbour cb index for an output site of parity p
   int* d_cb2lex = nullptr;  // [2][Vh]
+  int* d_blkmap = nullptr;  // fused-hop block -> chunk of sites (traversal order)
   // s-matrices (FP64 and FP32 copies), [MIX_COUNT][2][Ls][Ls]
   double* d_mix64 = nullptr;
   float* d_mix32 = nullptr;
+  int* d_sweep_meta = nullptr;     // [MIX_COUNT][2][4]
+  double* d_sweep64 = nullptr;     // [MIX_COUNT][2][kMaxStages][4][kLsPad]
+  float* d_sweep32 = nullptr;
+  std::vector<int> sweep_meta_host;
+  bool dense_mix = false;          // some sweep program failed its check: dense matrices
   std::vector<double> h_mix;
   // links per precision
   dwa::PrecFields prec[3];
@@ -196,6 +224,12 @@ struct dwa_ctx {
 };
 
 namespace dwa {
+
+// Sites per block of the fused hop kernel: 16 for the Ls with their own kernels
+// (4, 8, 12, 16), 8 for the generic kernel (Ls <= 32).
+inline int hop_sites_per_block(int Ls) {
+  return (Ls == 4 || Ls == 8 || Ls == 12 || Ls == 16) ? 16 : 8;
+}
 
 // kernel launchers (kernels.hip)
 struct HopOp {
@@ -235,6 +269,21 @@ int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
                       const DevScalars* s);
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* partials_a, int na,
                        const double* partials_b, int nb);
+
+// per-precision launchers (kcommon.h), instantiated in kernels_{f64,f32,bf16}.hip
+template <typename S> int launch_hop_p(dwa_ctx*, const HopOp&, int*);
+template <typename S> int launch_smix_p(dwa_ctx*, int, void*, const void*, const void*, double, int,
+                                        double*, int*);
+template <typename S> int launch_update1_p(dwa_ctx*, void*, void*, void*, const void*, const void*,
+                                           const DevScalars*, double*, int*);
+template <typename S> int launch_update2_p(dwa_ctx*, void*, void*, const void*, const DevScalars*);
+template <typename S> int norm2_p(dwa_ctx*, const void*, size_t, double*, int*);
+template <typename S> int axpby_p(dwa_ctx*, void*, double, const void*, double, size_t);
+template <typename S> int zero_p(dwa_ctx*, void*, size_t);
+template <typename S> int pack5_p(dwa_ctx*, void*, const void*, int, int);
+template <typename S> int unpack5_p(dwa_ctx*, void*, const void*, int, int);
+template <typename S> int pack_links_p(dwa_ctx*, void*, const void*);
+template <typename SO, typename SI> int convert_p(dwa_ctx*, void*, const void*, size_t, double);
 
 size_t field_elems(const dwa_ctx* ctx);  // Ls * 12 * Vh complex numbers
 void set_error(const std::string& msg);

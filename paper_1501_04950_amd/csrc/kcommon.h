@@ -1,0 +1,1075 @@
+// Device code of libdwa shared by the per-precision translation units
+// (kernels_f64.hip, kernels_f32.hip, kernels_bf16.hip): kernel templates and their
+// launchers.  Each unit instantiates the launchers for one storage precision.
+//
+// Field layout (one parity, "SoA"): element (s, comp, cb) of a 5D half field sits at
+// (s * 12 + comp) * Vh + cb, comp = spin * 3 + colour, so a wavefront of consecutive
+// checkerboard sites reads or writes one contiguous run per (s, comp).  Links of one
+// precision are [parity][mu][row*3+col][cb] with the antiperiodic time phase folded in.
+// nbr[p][dir][cb] is the checkerboard index (in the other parity) of the neighbour
+// x + mu (dir = mu) or x - mu (dir = 4 + mu) of the output site cb of parity p.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dwa_internal.h"
+
+namespace dwa {
+
+template <typename S>
+using RealOf = typename S::real;
+
+// the value a complex number has after a store/load round trip in storage S
+template <typename S>
+__device__ __forceinline__ cpx<RealOf<S>> as_stored(cpx<RealOf<S>> v) {
+  if constexpr (S::prec == DWA_BF16) {
+    return cmk<float>(bf16_to_f32(f32_to_bf16_rne(v.re)), bf16_to_f32(f32_to_bf16_rne(v.im)));
+  } else {
+    return v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wave64 + LDS block reduction of a double, fixed order (deterministic)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ void block_sum_to(double v, double* out_slot) {
+  __shared__ double wsum[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  if (lane == 0) wsum[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += wsum[i];
+    *out_slot = t;
+  }
+}
+
+// Scalar-loadable view of a read-only table: the constant address space tells the
+// compiler no store in the kernel can alias it, so wave-uniform reads become s_load.
+template <typename R>
+using cptr = const __attribute__((address_space(4))) R*;
+
+template <typename R>
+__device__ __forceinline__ cptr<R> as_const(const R* p) {
+  return (cptr<R>)(p);
+}
+
+// Apply one row of a per-chirality fifth-dimension matrix: sum_j M[i][j] v[j]; the row
+// is wave-uniform and read through scalar loads.
+template <typename R, int LSM>
+__device__ __forceinline__ cpx<R> mix_row_c(cptr<R> Mrow, const cpx<R>* v, int Ls) {
+  cpx<R> o = cmk<R>(0, 0);
+#pragma unroll
+  for (int j = 0; j < LSM; ++j)
+    if (j < Ls) {
+      const R mij = Mrow[j];
+      o.re = fma(mij, v[j].re, o.re);
+      o.im = fma(mij, v[j].im, o.im);
+    }
+  return o;
+}
+
+
+// ---------------------------------------------------------------------------
+// Site-local fifth-dimension operators as O(Ls) sweeps.  Each matrix kind is a fixed
+// product of at most three factors per chirality (diagonal, cyclic bidiagonal, cyclic
+// bidiagonal solve); the factor order is fixed here at compile time and the host
+// (build_smatrices) writes the coefficients of each factor in the same order.  The
+// coefficient rows are wave-uniform and come in through scalar loads.  v holds the Ls
+// values of one colour-spin component.
+
+template <typename R, int LSM>
+__device__ __forceinline__ void stage_scale(cpx<R>* v, cptr<R> A, int Ls) {
+#pragma unroll
+  for (int s = 0; s < LSM; ++s)
+    if (s < Ls) v[s] = A[s] * v[s];
+}
+
+// y_s = A_s x_s + B_s x_{s-1} (lower; y_0 takes B_0 x_{Ls-1}) or x_{s+1} (upper;
+// y_{Ls-1} takes B_{Ls-1} x_0)
+template <typename R, int LSM, bool LOWER>
+__device__ __forceinline__ void stage_bidiag(cpx<R>* v, cptr<R> A, cptr<R> B, int Ls) {
+  if constexpr (LOWER) {
+    cpx<R> xl = v[0];
+#pragma unroll
+    for (int s = 0; s < LSM; ++s)
+      if (s < Ls) xl = v[s];
+#pragma unroll
+    for (int s = LSM - 1; s >= 1; --s)
+      if (s < Ls) {
+        cpx<R> o = A[s] * v[s];
+        o.re = fma(B[s], v[s - 1].re, o.re);
+        o.im = fma(B[s], v[s - 1].im, o.im);
+        v[s] = o;
+      }
+    cpx<R> o = A[0] * v[0];
+    o.re = fma(B[0], xl.re, o.re);
+    o.im = fma(B[0], xl.im, o.im);
+    v[0] = o;
+  } else {
+    const cpx<R> x0 = v[0];
+#pragma unroll
+    for (int s = 0; s < LSM - 1; ++s)
+      if (s + 1 < Ls) {
+        cpx<R> o = A[s] * v[s];
+        o.re = fma(B[s], v[s + 1].re, o.re);
+        o.im = fma(B[s], v[s + 1].im, o.im);
+        v[s] = o;
+      }
+#pragma unroll
+    for (int s = 0; s < LSM; ++s)
+      if (s == Ls - 1) {
+        cpx<R> o = A[s] * v[s];
+        o.re = fma(B[s], x0.re, o.re);
+        o.im = fma(B[s], x0.im, o.im);
+        v[s] = o;
+      }
+  }
+}
+
+// Solve with a cyclic bidiagonal matrix (A = 1/d, B = e/d, C = f, W = 1/(1 - f_end)):
+// a sweep for the particular part, the closure value, and a correction pass.
+template <typename R, int LSM, bool LOWER>
+__device__ __forceinline__ void stage_solve(cpx<R>* v, cptr<R> A, cptr<R> B, cptr<R> C,
+                                            int Ls) {
+  const R W = A[3 * kLsPad];
+  if constexpr (LOWER) {
+    v[0] = A[0] * v[0];
+#pragma unroll
+    for (int s = 1; s < LSM; ++s)
+      if (s < Ls) {
+        cpx<R> o = A[s] * v[s];
+        o.re = fma(-B[s], v[s - 1].re, o.re);
+        o.im = fma(-B[s], v[s - 1].im, o.im);
+        v[s] = o;
+      }
+    cpx<R> Y = cmk<R>(0, 0);
+#pragma unroll
+    for (int s = 0; s < LSM; ++s)
+      if (s == Ls - 1) Y = W * v[s];
+#pragma unroll
+    for (int s = 0; s < LSM; ++s) {
+      if (s < Ls - 1) {
+        v[s].re = fma(C[s], Y.re, v[s].re);
+        v[s].im = fma(C[s], Y.im, v[s].im);
+      } else if (s == Ls - 1) {
+        v[s] = Y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < LSM; ++s)
+      if (s == Ls - 1) v[s] = A[s] * v[s];
+#pragma unroll
+    for (int s = LSM - 2; s >= 0; --s)
+      if (s < Ls - 1) {
+        cpx<R> o = A[s] * v[s];
+        o.re = fma(-B[s], v[s + 1].re, o.re);
+        o.im = fma(-B[s], v[s + 1].im, o.im);
+        v[s] = o;
+      }
+    const cpx<R> Y = W * v[0];
+    v[0] = Y;
+#pragma unroll
+    for (int s = 1; s < LSM; ++s)
+      if (s < Ls) {
+        v[s].re = fma(C[s], Y.re, v[s].re);
+        v[s].im = fma(C[s], Y.im, v[s].im);
+      }
+  }
+}
+
+// Tables of one matrix kind in the compute precision R:
+//   coef  [2][kMaxStages][4][kLsPad]   (chirality, stage, row A/B/C/W, slice)
+//   dense [2][Ls][Ls]
+struct MixTables {
+  const void* coef;
+  const void* dense;
+};
+
+// Apply matrix KIND of chirality CH (0 = P+, 1 = P-) to v.  For P+ the factors B and I_1
+// are lower cyclic bidiagonal and their transposes upper; for P- the other way round.
+template <typename R, int LSM, int KIND, int CH, bool DENSE>
+__device__ __forceinline__ void apply_mix(cpx<R>* v, int Ls, const MixTables& T) {
+  if constexpr (DENSE) {
+    cptr<R> M = as_const((const R*)T.dense + (size_t)CH * Ls * Ls);
+    cpx<R> y[LSM];
+#pragma unroll
+    for (int i = 0; i < LSM; ++i)
+      if (i < Ls) y[i] = mix_row_c<R, LSM>(M + i * Ls, v, Ls);
+#pragma unroll
+    for (int i = 0; i < LSM; ++i)
+      if (i < Ls) v[i] = y[i];
+  } else {
+    constexpr bool LOW = CH == 0;
+    cptr<R> c0 = as_const((const R*)T.coef + (size_t)CH * kMaxStages * 4 * kLsPad);
+    cptr<R> c1 = c0 + 4 * kLsPad;
+    if constexpr (KIND == MIX_BG) {  // B G
+      stage_scale<R, LSM>(v, c0, Ls);
+      stage_bidiag<R, LSM, LOW>(v, c1, c1 + kLsPad, Ls);
+    } else if constexpr (KIND == MIX_N) {  // B I_1^-1
+      stage_solve<R, LSM, LOW>(v, c0, c0 + kLsPad, c0 + 2 * kLsPad, Ls);
+      stage_bidiag<R, LSM, LOW>(v, c1, c1 + kLsPad, Ls);
+    } else if constexpr (KIND == MIX_GINV_IINV) {  // G^-1 I_1^-1
+      stage_solve<R, LSM, LOW>(v, c0, c0 + kLsPad, c0 + 2 * kLsPad, Ls);
+      stage_scale<R, LSM>(v, c1, Ls);
+    } else if constexpr (KIND == MIX_G5_IINVT_GINV) {  // g5 I_1^-T G^-1
+      stage_scale<R, LSM>(v, c0, Ls);
+      stage_solve<R, LSM, !LOW>(v, c1, c1 + kLsPad, c1 + 2 * kLsPad, Ls);
+    } else if constexpr (KIND == MIX_NT) {  // I_1^-T B^T
+      stage_bidiag<R, LSM, !LOW>(v, c0, c0 + kLsPad, Ls);
+      stage_solve<R, LSM, !LOW>(v, c1, c1 + kLsPad, c1 + 2 * kLsPad, Ls);
+    } else if constexpr (KIND == MIX_G_BT_G5) {  // G B^T g5
+      stage_bidiag<R, LSM, !LOW>(v, c0, c0 + kLsPad, Ls);
+      stage_scale<R, LSM>(v, c1, Ls);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One site of the Wilson hopping sum H psi (eq.(wilson) without the -1/2):
+//   H psi(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu),
+// in the chiral basis with the two-spinor projection: for each direction the
+// upper spins carry v = U h (or U^dag h) of the projected h, the lower spins a
+// fixed +-1/+-i recombination of v.
+template <typename S>
+__device__ __forceinline__ void hop_site(const typename S::elem* __restrict__ in,
+                                         const typename S::elem* __restrict__ links,
+                                         const int* __restrict__ nbr, int p, unsigned site,
+                                         unsigned s, unsigned Vh, cpx<RealOf<S>> acc[12]) {
+  using R = RealOf<S>;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = cmk<R>(0, 0);
+  const unsigned plane = 12u * Vh;
+  const typename S::elem* ins = in + size_t(s) * plane;
+  unsigned nbs[8];
+#pragma unroll
+  for (int dir = 0; dir < 8; ++dir) nbs[dir] = (unsigned)nbr[(p * 8 + dir) * Vh + site];
+  // the direction loop stays rolled: unrolled, the scheduler hoists all eight gathers
+  // (8 x 12 spinor + 8 x 9 link complex numbers) and the kernel spills in FP64
+#pragma unroll 1
+  for (int dir = 0; dir < 8; ++dir) {
+    const int mu = dir & 3;
+    const bool fwd = dir < 4;
+    const unsigned nb = nbs[dir];
+    cpx<R> ps[4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int co = 0; co < 3; ++co) ps[sp][co] = ld<S>(ins, (sp * 3 + co) * Vh + nb);
+    // projection h = psi_u -+ A psi_l
+    cpx<R> h[2][3];
+#pragma unroll
+    for (int co = 0; co < 3; ++co) {
+      const cpx<R> p0 = ps[0][co], p1 = ps[1][co], p2 = ps[2][co], p3 = ps[3][co];
+      if (mu == 0) {
+        h[0][co] = fwd ? p0 + mul_i(p3) : p0 - mul_i(p3);
+        h[1][co] = fwd ? p1 + mul_i(p2) : p1 - mul_i(p2);
+      } else if (mu == 1) {
+        h[0][co] = fwd ? p0 + p3 : p0 - p3;
+        h[1][co] = fwd ? p1 - p2 : p1 + p2;
+      } else if (mu == 2) {
+        h[0][co] = fwd ? p0 + mul_i(p2) : p0 - mul_i(p2);
+        h[1][co] = fwd ? p1 - mul_i(p3) : p1 + mul_i(p3);
+      } else {
+        h[0][co] = fwd ? p0 - p2 : p0 + p2;
+        h[1][co] = fwd ? p1 - p3 : p1 + p3;
+      }
+    }
+    // link: U_mu(x) from this parity, or U_mu(x-mu) from the other parity
+    const unsigned lsite = fwd ? site : nb;
+    const int lpar = fwd ? p : 1 - p;
+    const typename S::elem* L = links + size_t((lpar * 4 + mu) * 9) * Vh;
+    cpx<R> u[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = ld<S>(L, k * Vh + lsite);
+    cpx<R> v[2][3];
+#pragma unroll
+    for (int hs = 0; hs < 2; ++hs)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cpx<R> t = cmk<R>(0, 0);
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+          if (fwd) cmac(t, u[a * 3 + bb], h[hs][bb]);        // (U h)_a
+          else cmac_conj(t, u[bb * 3 + a], h[hs][bb]);       // (U^dag h)_a
+        }
+        v[hs][a] = t;
+      }
+    // reconstruct: upper spins += v; lower spins += fixed recombination of v
+#pragma unroll
+    for (int co = 0; co < 3; ++co) {
+      acc[0 * 3 + co] = acc[0 * 3 + co] + v[0][co];
+      acc[1 * 3 + co] = acc[1 * 3 + co] + v[1][co];
+      cpx<R> l0, l1;
+      if (mu == 0) {
+        l0 = fwd ? mul_mi(v[1][co]) : mul_i(v[1][co]);
+        l1 = fwd ? mul_mi(v[0][co]) : mul_i(v[0][co]);
+      } else if (mu == 1) {
+        l0 = fwd ? cmk<R>(-v[1][co].re, -v[1][co].im) : v[1][co];
+        l1 = fwd ? v[0][co] : cmk<R>(-v[0][co].re, -v[0][co].im);
+      } else if (mu == 2) {
+        l0 = fwd ? mul_mi(v[0][co]) : mul_i(v[0][co]);
+        l1 = fwd ? mul_i(v[1][co]) : mul_mi(v[1][co]);
+      } else {
+        l0 = fwd ? cmk<R>(-v[0][co].re, -v[0][co].im) : v[0][co];
+        l1 = fwd ? cmk<R>(-v[1][co].re, -v[1][co].im) : v[1][co];
+      }
+      acc[2 * 3 + co] = acc[2 * 3 + co] + l0;
+      acc[3 * 3 + co] = acc[3 * 3 + co] + l1;
+    }
+  }
+}
+
+struct HopDev {
+  const void* in;
+  void* out;
+  const void* pre;
+  const void* post;
+  const void* links;
+  const int* nbr;
+  MixTables mix;      // tables of the output fifth-dimension matrix
+  const int* blkmap;  // block -> chunk of NS sites, or null for the identity
+  double* partials;
+  double hop_coef, pre_coef, post_coef;
+  int parity_out;
+  int nslices;
+  unsigned Vh;
+};
+
+// Hop without a fifth-dimension mix: one thread per (site, slice).
+template <typename S>
+__global__ void __launch_bounds__(128) hop_plain_kernel(HopDev a) {
+  using R = RealOf<S>;
+  using E = typename S::elem;
+  const unsigned site = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned s = blockIdx.y;
+  double nrm = 0.0;
+  if (site < a.Vh) {
+    cpx<R> acc[12];
+    hop_site<S>((const E*)a.in, (const E*)a.links, a.nbr, a.parity_out, site, s, a.Vh, acc);
+    const size_t base = size_t(s) * 12 * a.Vh + site;
+    const R hc = (R)a.hop_coef, pc = (R)a.pre_coef, qc = (R)a.post_coef;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      cpx<R> o = hc * acc[k];
+      if (a.pre) o = o + pc * ld<S>((const E*)a.pre, base + size_t(k) * a.Vh);
+      if (a.post) o = o + qc * ld<S>((const E*)a.post, base + size_t(k) * a.Vh);
+      st<S>((E*)a.out, base + size_t(k) * a.Vh, o);
+      nrm += (double)norm2(o);
+    }
+  }
+  if (a.partials) block_sum_to(nrm, &a.partials[blockIdx.y * gridDim.x + blockIdx.x]);
+}
+
+// Blocks are dealt to the 8 XCDs round robin; remap so that each XCD works on one
+// contiguous range of checkerboard sites and its L2 sees the neighbours' reuse.
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nblocks) {
+  if (nblocks % 8u) return b;
+  return (b % 8u) * (nblocks / 8u) + b / 8u;
+}
+
+
+// One site of H psi with the neighbour indices and links of the block in LDS.
+template <typename S>
+__device__ __forceinline__ void hop_site_lds(const typename S::elem* __restrict__ ins,
+                                             const unsigned* lnbr, const cpx<RealOf<S>>* llink,
+                                             int sl, int NS, unsigned Vh, cpx<RealOf<S>> acc[12]) {
+  using R = RealOf<S>;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = cmk<R>(0, 0);
+  // fully unrolled: with the links in LDS only the spinor gathers are global loads,
+  // and compile-time directions remove every branch on mu and on the hop sign
+#pragma unroll
+  for (int dir = 0; dir < 8; ++dir) {
+    const int mu = dir & 3;
+    const bool fwd = dir < 4;
+    const unsigned nb = lnbr[dir * NS + sl];
+    cpx<R> ps[4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int co = 0; co < 3; ++co) ps[sp][co] = ld<S>(ins, (sp * 3 + co) * Vh + nb);
+    cpx<R> h[2][3];
+#pragma unroll
+    for (int co = 0; co < 3; ++co) {
+      const cpx<R> p0 = ps[0][co], p1 = ps[1][co], p2 = ps[2][co], p3 = ps[3][co];
+      if (mu == 0) {
+        h[0][co] = fwd ? p0 + mul_i(p3) : p0 - mul_i(p3);
+        h[1][co] = fwd ? p1 + mul_i(p2) : p1 - mul_i(p2);
+      } else if (mu == 1) {
+        h[0][co] = fwd ? p0 + p3 : p0 - p3;
+        h[1][co] = fwd ? p1 - p2 : p1 + p2;
+      } else if (mu == 2) {
+        h[0][co] = fwd ? p0 + mul_i(p2) : p0 - mul_i(p2);
+        h[1][co] = fwd ? p1 - mul_i(p3) : p1 + mul_i(p3);
+      } else {
+        h[0][co] = fwd ? p0 - p2 : p0 + p2;
+        h[1][co] = fwd ? p1 - p3 : p1 + p3;
+      }
+    }
+    cpx<R> u[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = llink[(dir * 9 + k) * NS + sl];
+    cpx<R> v[2][3];
+#pragma unroll
+    for (int hs = 0; hs < 2; ++hs)
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa) {
+        cpx<R> t = cmk<R>(0, 0);
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+          if (fwd) cmac(t, u[aa * 3 + bb], h[hs][bb]);
+          else cmac_conj(t, u[bb * 3 + aa], h[hs][bb]);
+        }
+        v[hs][aa] = t;
+      }
+#pragma unroll
+    for (int co = 0; co < 3; ++co) {
+      acc[0 * 3 + co] = acc[0 * 3 + co] + v[0][co];
+      acc[1 * 3 + co] = acc[1 * 3 + co] + v[1][co];
+      cpx<R> l0, l1;
+      if (mu == 0) {
+        l0 = fwd ? mul_mi(v[1][co]) : mul_i(v[1][co]);
+        l1 = fwd ? mul_mi(v[0][co]) : mul_i(v[0][co]);
+      } else if (mu == 1) {
+        l0 = fwd ? cmk<R>(-v[1][co].re, -v[1][co].im) : v[1][co];
+        l1 = fwd ? v[0][co] : cmk<R>(-v[0][co].re, -v[0][co].im);
+      } else if (mu == 2) {
+        l0 = fwd ? mul_mi(v[0][co]) : mul_i(v[0][co]);
+        l1 = fwd ? mul_i(v[1][co]) : mul_mi(v[1][co]);
+      } else {
+        l0 = fwd ? cmk<R>(-v[0][co].re, -v[0][co].im) : v[0][co];
+        l1 = fwd ? cmk<R>(-v[1][co].re, -v[1][co].im) : v[1][co];
+      }
+      acc[2 * 3 + co] = acc[2 * 3 + co] + l0;
+      acc[3 * 3 + co] = acc[3 * 3 + co] + l1;
+    }
+  }
+}
+
+// LDS footprint of hop_mix_kernel in bytes.
+template <typename R>
+__host__ __device__ constexpr size_t hop_mix_lds_bytes(int NS, int Ls) {
+  return (size_t(Ls) * 12 * (NS + 1) * sizeof(cpx<R>) > size_t(72) * NS * sizeof(cpx<R>)
+              ? size_t(Ls) * 12 * (NS + 1) * sizeof(cpx<R>)
+              : size_t(72) * NS * sizeof(cpx<R>)) +
+         size_t(8) * NS * sizeof(unsigned);
+}
+
+// Phase 2 of hop_mix_kernel for one (site, component) of chirality CH: read the Ls
+// values from the tile, apply the fifth-dimension matrix, add the post term, store.
+template <typename S, int NS, int LSM, int MODE, int KIND, int CH, bool DENSE>
+__device__ __forceinline__ double hop_mix_out(const HopDev& a, const cpx<RealOf<S>>* tile,
+                                              unsigned site0, int Ls, int lt) {
+  using R = RealOf<S>;
+  using E = typename S::elem;
+  constexpr int NSP = NS + 1;
+  const int sl = lt % NS, comp = CH * 6 + lt / NS;
+  const unsigned site = site0 + sl;
+  cpx<R> v[LSM];
+#pragma unroll
+  for (int j = 0; j < LSM; ++j)
+    if (j < Ls) v[j] = tile[(j * 12 + comp) * NSP + sl];
+  apply_mix<R, LSM, KIND, CH, DENSE>(v, Ls, a.mix);
+  double nrm = 0.0;
+  if (site < a.Vh) {
+    const R qc = (R)a.post_coef;
+#pragma unroll
+    for (int i = 0; i < LSM; ++i)
+      if (i < Ls) {
+        cpx<R> o = v[i];
+        const unsigned idx = (unsigned(i) * 12u + unsigned(comp)) * a.Vh + site;
+        if (MODE == 1) o = o + qc * ld<S>((const E*)a.post, idx);
+        st<S>((E*)a.out, idx, o);
+        nrm += (double)norm2(o);
+      }
+  }
+  return nrm;
+}
+
+// Hop followed by a dense fifth-dimension mix, one block per NS checkerboard sites and
+// all Ls slices.
+//   Phase 0: the block stages the 8 neighbour indices and 72 link entries of its sites
+//            in LDS (each link is read from HBM once per block, not once per slice).
+//   Phase 1: thread (site, s) computes h' = hop_coef * H in (+ pre_coef * pre) and
+//            writes it to an LDS tile [s][comp][site] (padded rows; it reuses the link
+//            area once every thread is past the hop).
+//   Phase 2: thread (site, colour-spin component) holds the Ls values of that component
+//            of each chirality in turn in registers and applies the Ls x Ls matrix; the
+//            chirality loop is uniform, so matrix rows come in through scalar loads.  With
+//            enough threads the output rows are split into groups of whole wavefronts.
+// The block order comes from a host-built table that walks each XCD's share of the
+// lattice slab by slab, keeping the neighbours' reuse distance inside one XCD's L2.
+// LS > 0: Ls is the compile-time LS; LS == 0: runtime Ls <= 32.
+// MODE selects the epilogue at compile time so that each use is its own kernel:
+//   0: out = M H in                 (first hop of D_bb / D_bb^dag)
+//   1: out = M (hop_coef H in) + post_coef post   (second hop, with the x term)
+//   2: out = M (hop_coef H in + pre_coef pre)     (Schur prep and reconstruction)
+template <typename S, int NS, int LS, int MODE, int KIND, bool DENSE>
+__global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a) {
+  using R = RealOf<S>;
+  using E = typename S::elem;
+  constexpr int LSM = LS > 0 ? LS : 32;
+  constexpr int NSP = NS + 1;
+  extern __shared__ char smem_raw[];
+  const int Ls = LS > 0 ? LS : a.nslices;
+  cpx<R>* tile = reinterpret_cast<cpx<R>*>(smem_raw);
+  cpx<R>* llink = tile;  // phase 0/1 only
+  const size_t region = size_t(Ls) * 12 * NSP * sizeof(cpx<R>) > size_t(72) * NS * sizeof(cpx<R>)
+                            ? size_t(Ls) * 12 * NSP * sizeof(cpx<R>)
+                            : size_t(72) * NS * sizeof(cpx<R>);
+  unsigned* lnbr = reinterpret_cast<unsigned*>(smem_raw + region);
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned site0 = (a.blkmap ? (unsigned)a.blkmap[blk] : blk) * NS;
+  const int p = a.parity_out;
+  const unsigned Vh = a.Vh;
+
+  // phase 0: neighbour indices, then links
+  for (int e = threadIdx.x; e < 8 * NS; e += blockDim.x) {
+    const int dir = e / NS, sl = e % NS;
+    const unsigned site = site0 + sl;
+    lnbr[e] = site < Vh ? (unsigned)a.nbr[(p * 8 + dir) * Vh + site] : 0u;
+  }
+  __syncthreads();
+  {
+    const E* L = (const E*)a.links;
+    for (int e = threadIdx.x; e < 72 * NS; e += blockDim.x) {
+      const int sl = e % NS, r = e / NS, k = r % 9, dir = r / 9, mu = dir & 3;
+      const unsigned site = site0 + sl;
+      cpx<R> v = cmk<R>(0, 0);
+      if (site < Vh) {
+        const bool fwd = dir < 4;
+        const unsigned lsite = fwd ? site : lnbr[dir * NS + sl];
+        const int lpar = fwd ? p : 1 - p;
+        v = ld<S>(L, ((lpar * 4 + mu) * 9 + k) * Vh + lsite);
+      }
+      llink[(dir * 9 + k) * NS + sl] = v;
+    }
+  }
+  __syncthreads();
+
+  // phase 1: hop
+  const int sl1 = threadIdx.x % NS, s1 = threadIdx.x / NS;
+  const unsigned site1 = site0 + sl1;
+  cpx<R> acc[12];
+  const bool act1 = s1 < Ls && site1 < Vh;
+  if (act1) {
+    hop_site_lds<S>((const E*)a.in + size_t(s1) * 12 * Vh, lnbr, llink, sl1, NS, Vh, acc);
+    if (MODE != 0) {
+      const R hc = (R)a.hop_coef, pc = (R)a.pre_coef;
+      const unsigned base = unsigned(s1) * 12u * Vh + site1;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        cpx<R> o = hc * acc[k];
+        if (MODE == 2) o = o + pc * ld<S>((const E*)a.pre, base + unsigned(k) * Vh);
+        acc[k] = o;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = cmk<R>(0, 0);
+  }
+  __syncthreads();  // every thread is done with the links
+  if (s1 < Ls) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) tile[(s1 * 12 + k) * NSP + sl1] = acc[k];
+  }
+  __syncthreads();
+
+  // phase 2: fifth-dimension mix.  Work items are (chirality, site, component of that
+  // chirality); PH is a whole number of wavefronts, so the chirality is the same on
+  // every lane of a wave and the branch on it is uniform.
+  double nrm = 0.0;
+  constexpr int PH = ((NS * 6 + 63) / 64) * 64;
+  for (int t = threadIdx.x; t < 2 * PH; t += blockDim.x) {
+    const int ch = __builtin_amdgcn_readfirstlane(t / PH), lt = t % PH;
+    if (lt >= NS * 6) continue;
+    if (ch == 0)
+      nrm += hop_mix_out<S, NS, LSM, MODE, KIND, 0, DENSE>(a, tile, site0, Ls, lt);
+    else
+      nrm += hop_mix_out<S, NS, LSM, MODE, KIND, 1, DENSE>(a, tile, site0, Ls, lt);
+  }
+  if (a.partials) block_sum_to(nrm, &a.partials[blockIdx.x]);
+}
+
+// Site-local kernels run one thread per (site, colour-spin component of one chirality)
+// and loop over the two chiralities, so the matrix rows are wave-uniform.
+#define DWA_SITE_THREAD                                                       \
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;                   \
+  const bool live = t < 6u * Vh;                                              \
+  const unsigned c6 = live ? t / Vh : 0u, site = live ? t % Vh : 0u
+
+// Site-local mix: out[s] = sum_s' M[ch][s][s'] in[s'] (+ post_coef * post[s]).
+template <typename S, int LS, int KIND, bool DENSE>
+__global__ void __launch_bounds__(256) smix_kernel(typename S::elem* __restrict__ out,
+                                                   const typename S::elem* __restrict__ in,
+                                                   const typename S::elem* __restrict__ post,
+                                                   double post_coef, MixTables P, int Ls_rt,
+                                                   unsigned Vh, double* partials) {
+  using R = RealOf<S>;
+  constexpr int LSM = LS > 0 ? LS : 32;
+  const int Ls = LS > 0 ? LS : Ls_rt;
+  DWA_SITE_THREAD;
+  double nrm = 0.0;
+  if (live) {
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      const unsigned comp = ch * 6 + c6;
+      cpx<R> v[LSM];
+#pragma unroll
+      for (int j = 0; j < LSM; ++j)
+        if (j < Ls) v[j] = ld<S>(in, (size_t(j) * 12 + comp) * Vh + site);
+      if (ch == 0) apply_mix<R, LSM, KIND, 0, DENSE>(v, Ls, P);
+      else apply_mix<R, LSM, KIND, 1, DENSE>(v, Ls, P);
+#pragma unroll
+      for (int i = 0; i < LSM; ++i)
+        if (i < Ls) {
+          cpx<R> o = v[i];
+          const size_t idx = (size_t(i) * 12 + comp) * Vh + site;
+          if (post) o = o + (R)post_coef * ld<S>(post, idx);
+          st<S>(out, idx, o);
+          nrm += (double)norm2(o);
+        }
+    }
+  }
+  if (partials) block_sum_to(nrm, &partials[blockIdx.x]);
+}
+
+// CGLS update 1: x += a p ; r -= a q ; |r|^2 ; w = (g5 I^-T G^-1) r
+template <typename S, int LS, bool DENSE>
+__global__ void __launch_bounds__(256) cg_update1_kernel(typename S::elem* __restrict__ x,
+                                                         typename S::elem* __restrict__ r,
+                                                         typename S::elem* __restrict__ w,
+                                                         const typename S::elem* __restrict__ p,
+                                                         const typename S::elem* __restrict__ q,
+                                                         const DevScalars* __restrict__ sc,
+                                                         MixTables P, int Ls_rt, unsigned Vh,
+                                                         double* partials) {
+  using R = RealOf<S>;
+  constexpr int LSM = LS > 0 ? LS : 32;
+  const int Ls = LS > 0 ? LS : Ls_rt;
+  DWA_SITE_THREAD;
+  double nrm = 0.0;
+  if (live) {
+    const R a = (R)sc->a;
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      const unsigned comp = ch * 6 + c6;
+      cpx<R> rv[LSM];
+#pragma unroll
+      for (int j = 0; j < LSM; ++j)
+        if (j < Ls) {
+          const size_t idx = (size_t(j) * 12 + comp) * Vh + site;
+          cpx<R> xv = ld<S>(x, idx), pv = ld<S>(p, idx), qv = ld<S>(q, idx), rr = ld<S>(r, idx);
+          xv = xv + a * pv;
+          rr = rr - a * qv;
+          st<S>(x, idx, xv);
+          st<S>(r, idx, rr);
+          rv[j] = as_stored<S>(rr);  // premix the value as stored
+          nrm += (double)norm2(rv[j]);
+        }
+      if (ch == 0) apply_mix<R, LSM, MIX_G5_IINVT_GINV, 0, DENSE>(rv, Ls, P);
+      else apply_mix<R, LSM, MIX_G5_IINVT_GINV, 1, DENSE>(rv, Ls, P);
+#pragma unroll
+      for (int i = 0; i < LSM; ++i)
+        if (i < Ls) st<S>(w, (size_t(i) * 12 + comp) * Vh + site, rv[i]);
+    }
+  }
+  if (partials) block_sum_to(nrm, &partials[blockIdx.x]);
+}
+
+// CGLS update 2: p = z + beta p ; u = (B G) p
+template <typename S, int LS, bool DENSE>
+__global__ void __launch_bounds__(256) cg_update2_kernel(typename S::elem* __restrict__ p,
+                                                         typename S::elem* __restrict__ u,
+                                                         const typename S::elem* __restrict__ z,
+                                                         const DevScalars* __restrict__ sc,
+                                                         MixTables P, int Ls_rt, unsigned Vh) {
+  using R = RealOf<S>;
+  constexpr int LSM = LS > 0 ? LS : 32;
+  const int Ls = LS > 0 ? LS : Ls_rt;
+  DWA_SITE_THREAD;
+  if (!live) return;
+  const R beta = (R)sc->beta;
+#pragma unroll
+  for (int ch = 0; ch < 2; ++ch) {
+    const unsigned comp = ch * 6 + c6;
+    cpx<R> pv[LSM];
+#pragma unroll
+    for (int j = 0; j < LSM; ++j)
+      if (j < Ls) {
+        const size_t idx = (size_t(j) * 12 + comp) * Vh + site;
+        cpx<R> v = ld<S>(z, idx) + beta * ld<S>(p, idx);
+        st<S>(p, idx, v);
+        pv[j] = as_stored<S>(v);
+      }
+    if (ch == 0) apply_mix<R, LSM, MIX_BG, 0, DENSE>(pv, Ls, P);
+    else apply_mix<R, LSM, MIX_BG, 1, DENSE>(pv, Ls, P);
+#pragma unroll
+    for (int i = 0; i < LSM; ++i)
+      if (i < Ls) st<S>(u, (size_t(i) * 12 + comp) * Vh + site, pv[i]);
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) norm2_kernel(const typename S::elem* __restrict__ x, size_t n,
+                                                    double* partials) {
+  double v = 0.0;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x)
+    v += (double)norm2(ld<S>(x, i));
+  block_sum_to(v, &partials[blockIdx.x]);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) axpby_kernel(typename S::elem* __restrict__ y, double a,
+                                                    const typename S::elem* __restrict__ x, double b,
+                                                    size_t n) {
+  using R = RealOf<S>;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    cpx<R> o = (R)a * ld<S>(x, i);
+    if (b != 0.0) o = o + (R)b * ld<S>(y, i);
+    st<S>(y, i, o);
+  }
+}
+
+template <typename SO, typename SI>
+__global__ void __launch_bounds__(256) convert_kernel(typename SO::elem* __restrict__ out,
+                                                      const typename SI::elem* __restrict__ in,
+                                                      size_t n, double scale) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    cpx<RealOf<SI>> v = ld<SI>(in, i);
+    // scale and round in FP64 / FP32 as the output needs
+    cpx<RealOf<SO>> o = cmk<RealOf<SO>>((RealOf<SO>)(scale * (double)v.re),
+                                        (RealOf<SO>)(scale * (double)v.im));
+    st<SO>(out, i, o);
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) zero_kernel(typename S::elem* __restrict__ p, size_t n) {
+  using R = RealOf<S>;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x)
+    st<S>(p, i, cmk<R>(0, 0));
+}
+
+// canonical complex128 [n][V][12] -> SoA [n][12][Vh] of one parity
+template <typename S>
+__global__ void __launch_bounds__(256) pack5_kernel(typename S::elem* __restrict__ dst,
+                                                    const double2* __restrict__ src,
+                                                    const int* __restrict__ cb2lex, int parity,
+                                                    int nslices, unsigned Vh, unsigned V) {
+  using R = RealOf<S>;
+  const size_t n = size_t(nslices) * 12 * Vh;
+  for (size_t t = blockIdx.x * size_t(blockDim.x) + threadIdx.x; t < n;
+       t += size_t(gridDim.x) * blockDim.x) {
+    const unsigned cb = t % Vh;
+    const size_t sc = t / Vh;
+    const unsigned comp = sc % 12, s = sc / 12;
+    const unsigned lex = (unsigned)cb2lex[parity * Vh + cb];
+    const double2 v = src[(size_t(s) * V + lex) * 12 + comp];
+    st<S>(dst, t, cmk<R>((R)v.x, (R)v.y));
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) unpack5_kernel(double2* __restrict__ dst,
+                                                      const typename S::elem* __restrict__ src,
+                                                      const int* __restrict__ cb2lex, int parity,
+                                                      int nslices, unsigned Vh, unsigned V) {
+  const size_t n = size_t(nslices) * 12 * Vh;
+  for (size_t t = blockIdx.x * size_t(blockDim.x) + threadIdx.x; t < n;
+       t += size_t(gridDim.x) * blockDim.x) {
+    const unsigned cb = t % Vh;
+    const size_t sc = t / Vh;
+    const unsigned comp = sc % 12, s = sc / 12;
+    const unsigned lex = (unsigned)cb2lex[parity * Vh + cb];
+    const auto v = ld<S>(src, t);
+    dst[(size_t(s) * V + lex) * 12 + comp] = make_double2((double)v.re, (double)v.im);
+  }
+}
+
+// canonical links [4][V][9] complex128 -> [p][mu][9][Vh], time phase folded
+template <typename S>
+__global__ void __launch_bounds__(256) pack_links_kernel(typename S::elem* __restrict__ dst,
+                                                         const double2* __restrict__ src, int Lx,
+                                                         int Ly, int Lz, int Lt, int apbc,
+                                                         unsigned V) {
+  using R = RealOf<S>;
+  const unsigned Vh = V / 2;
+  const size_t n = size_t(4) * V;
+  for (size_t t = blockIdx.x * size_t(blockDim.x) + threadIdx.x; t < n;
+       t += size_t(gridDim.x) * blockDim.x) {
+    const unsigned lex = t % V, mu = t / V;
+    unsigned r = lex;
+    const unsigned x = r % Lx;
+    r /= Lx;
+    const unsigned y = r % Ly;
+    r /= Ly;
+    const unsigned z = r % Lz;
+    const unsigned tt = r / Lz;
+    const unsigned par = (x + y + z + tt) & 1u, cb = lex >> 1;
+    const double sign = (apbc && mu == 3 && tt == (unsigned)(Lt - 1)) ? -1.0 : 1.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 v = src[(size_t(mu) * V + lex) * 9 + k];
+      st<S>(dst, (size_t(par * 4 + mu) * 9 + k) * Vh + cb,
+            cmk<R>((R)(sign * v.x), (R)(sign * v.y)));
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// launchers of one storage precision S (explicitly instantiated once per precision)
+
+inline int grid_for(size_t n, int block, int cap = 65536) {
+  size_t g = (n + block - 1) / block;
+  if (g > (size_t)cap) g = cap;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <typename S>
+MixTables mix_tables(dwa_ctx* ctx, int kind) {
+  MixTables T;
+  const size_t coff = size_t(kind) * 2 * kMaxStages * 4 * kLsPad;
+  const size_t doff = size_t(kind) * 2 * ctx->Ls * ctx->Ls;
+  if (S::prec == DWA_F64) {
+    T.coef = ctx->d_sweep64 + coff;
+    T.dense = ctx->d_mix64 + doff;
+  } else {
+    T.coef = ctx->d_sweep32 + coff;
+    T.dense = ctx->d_mix32 + doff;
+  }
+  return T;
+}
+
+// Ls values with their own compiled kernels; any other Ls <= 32 runs the generic one,
+// which is also the only one compiled with the dense fallback.
+#define DWA_LS_DISPATCH(Ls, dense, M) \
+  if (dense) {                        \
+    M(0, true);                       \
+  } else {                            \
+    switch (Ls) {                     \
+      case 4: M(4, false); break;     \
+      case 8: M(8, false); break;     \
+      case 12: M(12, false); break;   \
+      case 16: M(16, false); break;   \
+      default: M(0, false); break;    \
+    }                                 \
+  }
+
+template <typename S, int MODE, int KIND>
+void launch_hop_mix_mk(dwa_ctx* ctx, const HopDev& a, unsigned grid, dim3 block, size_t shm) {
+#define DWA_HOPMIX(LSV, DV)                                                                   \
+  {                                                                                           \
+    constexpr int NSV = LSV > 0 ? 16 : 8;                                                     \
+    hipLaunchKernelGGL((hop_mix_kernel<S, NSV, LSV, MODE, KIND, DV>), dim3(grid), block, shm, \
+                       ctx->stream, a);                                                       \
+  }
+  DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_HOPMIX)
+#undef DWA_HOPMIX
+}
+
+template <typename S>
+int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
+  HopDev a;
+  a.in = op.in;
+  a.out = op.out;
+  a.pre = op.pre;
+  a.post = op.post;
+  a.links = ctx->prec[S::prec].links;
+  a.nbr = ctx->d_nbr;
+  a.mix = mix_tables<S>(ctx, op.mix);
+  a.partials = op.partials;
+  a.blkmap = ctx->d_blkmap;
+  a.hop_coef = op.hop_coef;
+  a.pre_coef = op.pre_coef;
+  a.post_coef = op.post_coef;
+  a.parity_out = op.parity_out;
+  a.nslices = op.nslices;
+  a.Vh = (unsigned)ctx->Vh;
+  if (op.mix == MIX_IDENTITY) {
+    dim3 grid((unsigned)((ctx->Vh + 127) / 128), (unsigned)op.nslices);
+    hipLaunchKernelGGL(hop_plain_kernel<S>, grid, dim3(128), 0, ctx->stream, a);
+    if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
+    return hip_fail(hipGetLastError(), "hop kernel launch");
+  }
+  const int Ls = op.nslices;
+  if (Ls != ctx->Ls) {
+    set_error("fused hop runs on the context's Ls slices");
+    return DWA_EINVAL;
+  }
+  const int NS = ctx->dense_mix ? 8 : hop_sites_per_block(Ls);
+  const unsigned grid = (unsigned)((ctx->Vh + NS - 1) / NS);
+  const size_t shm = hop_mix_lds_bytes<RealOf<S>>(NS, Ls);
+  const dim3 block(NS * Ls);
+  const int mode = op.pre ? 2 : (op.post ? 1 : 0);
+  if (op.pre && op.post) {
+    set_error("hop with both pre and post terms is not supported");
+    return DWA_EINVAL;
+  }
+  if (mode == 0 && op.hop_coef != 1.0) {
+    set_error("plain fused hop takes hop_coef = 1");
+    return DWA_EINVAL;
+  }
+  if (mode == 0 && op.mix == MIX_N) launch_hop_mix_mk<S, 0, MIX_N>(ctx, a, grid, block, shm);
+  else if (mode == 0 && op.mix == MIX_NT) launch_hop_mix_mk<S, 0, MIX_NT>(ctx, a, grid, block, shm);
+  else if (mode == 0 && op.mix == MIX_GINV_IINV) launch_hop_mix_mk<S, 0, MIX_GINV_IINV>(ctx, a, grid, block, shm);
+  else if (mode == 0 && op.mix == MIX_G_BT_G5) launch_hop_mix_mk<S, 0, MIX_G_BT_G5>(ctx, a, grid, block, shm);
+  else if (mode == 1 && op.mix == MIX_GINV_IINV) launch_hop_mix_mk<S, 1, MIX_GINV_IINV>(ctx, a, grid, block, shm);
+  else if (mode == 1 && op.mix == MIX_G_BT_G5) launch_hop_mix_mk<S, 1, MIX_G_BT_G5>(ctx, a, grid, block, shm);
+  else if (mode == 2 && op.mix == MIX_GINV_IINV && S::prec == DWA_F64)
+    launch_hop_mix_mk<S, 2, MIX_GINV_IINV>(ctx, a, grid, block, shm);
+  else {
+    set_error("fused hop: unsupported combination of output matrix and epilogue");
+    return DWA_EINVAL;
+  }
+  if (nblocks_out) *nblocks_out = (int)grid;
+  return hip_fail(hipGetLastError(), "hop kernel launch");
+}
+
+template <typename S, int KIND>
+void launch_smix_k(dwa_ctx* ctx, void* out, const void* in, const void* post, double post_coef,
+                   double* partials, int grid) {
+  using E = typename S::elem;
+  const MixTables T = mix_tables<S>(ctx, KIND);
+  const unsigned Vh = (unsigned)ctx->Vh;
+#define DWA_SMIX(LSV, DV)                                                                    \
+  hipLaunchKernelGGL((smix_kernel<S, LSV, KIND, DV>), dim3(grid), dim3(256), 0, ctx->stream, \
+                     (E*)out, (const E*)in, (const E*)post, post_coef, T, ctx->Ls, Vh, partials)
+  DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_SMIX)
+#undef DWA_SMIX
+}
+
+template <typename S>
+int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* post,
+                  double post_coef, int nslices, double* partials, int* nblocks_out) {
+  if (nslices != ctx->Ls) {
+    set_error("site-local mix runs on the context's Ls slices");
+    return DWA_EINVAL;
+  }
+  const int grid = (int)((6u * (unsigned)ctx->Vh + 255) / 256);
+  if (mix == MIX_BG) launch_smix_k<S, MIX_BG>(ctx, out, in, post, post_coef, partials, grid);
+  else if (mix == MIX_N) launch_smix_k<S, MIX_N>(ctx, out, in, post, post_coef, partials, grid);
+  else if (mix == MIX_G5_IINVT_GINV)
+    launch_smix_k<S, MIX_G5_IINVT_GINV>(ctx, out, in, post, post_coef, partials, grid);
+  else {
+    set_error("site-local mix: unsupported matrix kind");
+    return DWA_EINVAL;
+  }
+  if (nblocks_out) *nblocks_out = grid;
+  return hip_fail(hipGetLastError(), "smix kernel launch");
+}
+
+template <typename S>
+int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, const void* q,
+                     const DevScalars* s, double* partials, int* nblocks) {
+  using E = typename S::elem;
+  const unsigned Vh = (unsigned)ctx->Vh;
+  const int grid = (int)((6u * Vh + 255) / 256);
+  const MixTables T = mix_tables<S>(ctx, MIX_G5_IINVT_GINV);
+#define DWA_U1(LSV, DV)                                                                         \
+  hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV>), dim3(grid), dim3(256), 0, ctx->stream,    \
+                     (E*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T, ctx->Ls, Vh, partials)
+  DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_U1)
+#undef DWA_U1
+  if (nblocks) *nblocks = grid;
+  return hip_fail(hipGetLastError(), "cg update1 launch");
+}
+
+template <typename S>
+int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevScalars* s) {
+  using E = typename S::elem;
+  const unsigned Vh = (unsigned)ctx->Vh;
+  const int grid = (int)((6u * Vh + 255) / 256);
+  const MixTables T = mix_tables<S>(ctx, MIX_BG);
+#define DWA_U2(LSV, DV)                                                                      \
+  hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV>), dim3(grid), dim3(256), 0, ctx->stream, \
+                     (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh)
+  DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_U2)
+#undef DWA_U2
+  return hip_fail(hipGetLastError(), "cg update2 launch");
+}
+
+template <typename S>
+int norm2_p(dwa_ctx* ctx, const void* x, size_t n, double* partials, int* nblocks) {
+  const int grid = grid_for(n, 256, 2048);
+  hipLaunchKernelGGL(norm2_kernel<S>, dim3(grid), dim3(256), 0, ctx->stream,
+                     (const typename S::elem*)x, n, partials);
+  *nblocks = grid;
+  return hip_fail(hipGetLastError(), "norm2 launch");
+}
+template <typename S>
+int axpby_p(dwa_ctx* ctx, void* y, double a, const void* x, double b, size_t n) {
+  hipLaunchKernelGGL(axpby_kernel<S>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
+                     (typename S::elem*)y, a, (const typename S::elem*)x, b, n);
+  return hip_fail(hipGetLastError(), "axpby launch");
+}
+template <typename S>
+int zero_p(dwa_ctx* ctx, void* p, size_t n) {
+  hipLaunchKernelGGL(zero_kernel<S>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
+                     (typename S::elem*)p, n);
+  return hip_fail(hipGetLastError(), "zero launch");
+}
+template <typename S>
+int pack5_p(dwa_ctx* ctx, void* dst, const void* src, int parity, int nslices) {
+  const size_t n = size_t(nslices) * 12 * ctx->Vh;
+  hipLaunchKernelGGL(pack5_kernel<S>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
+                     (typename S::elem*)dst, (const double2*)src, ctx->d_cb2lex, parity, nslices,
+                     (unsigned)ctx->Vh, (unsigned)ctx->V);
+  return hip_fail(hipGetLastError(), "pack5 launch");
+}
+template <typename S>
+int unpack5_p(dwa_ctx* ctx, void* dst, const void* src, int parity, int nslices) {
+  const size_t n = size_t(nslices) * 12 * ctx->Vh;
+  hipLaunchKernelGGL(unpack5_kernel<S>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
+                     (double2*)dst, (const typename S::elem*)src, ctx->d_cb2lex, parity, nslices,
+                     (unsigned)ctx->Vh, (unsigned)ctx->V);
+  return hip_fail(hipGetLastError(), "unpack5 launch");
+}
+template <typename S>
+int pack_links_p(dwa_ctx* ctx, void* dst, const void* src) {
+  const size_t n = size_t(4) * ctx->V;
+  hipLaunchKernelGGL(pack_links_kernel<S>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
+                     (typename S::elem*)dst, (const double2*)src, ctx->dims[0], ctx->dims[1],
+                     ctx->dims[2], ctx->dims[3], ctx->antiperiodic_t, (unsigned)ctx->V);
+  return hip_fail(hipGetLastError(), "pack links launch");
+}
+template <typename SO, typename SI>
+int convert_p(dwa_ctx* ctx, void* out, const void* in, size_t n, double scale) {
+  hipLaunchKernelGGL((convert_kernel<SO, SI>), dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
+                     (typename SO::elem*)out, (const typename SI::elem*)in, n, scale);
+  return hip_fail(hipGetLastError(), "convert launch");
+}
+
+#define DWA_INSTANTIATE_PRECISION(S)                                                            \
+  template int launch_hop_p<S>(dwa_ctx*, const HopOp&, int*);                                  \
+  template int launch_smix_p<S>(dwa_ctx*, int, void*, const void*, const void*, double, int,    \
+                                double*, int*);                                                 \
+  template int launch_update1_p<S>(dwa_ctx*, void*, void*, void*, const void*, const void*,     \
+                                   const DevScalars*, double*, int*);                           \
+  template int launch_update2_p<S>(dwa_ctx*, void*, void*, const void*, const DevScalars*);     \
+  template int norm2_p<S>(dwa_ctx*, const void*, size_t, double*, int*);                        \
+  template int axpby_p<S>(dwa_ctx*, void*, double, const void*, double, size_t);                \
+  template int zero_p<S>(dwa_ctx*, void*, size_t);                                              \
+  template int pack5_p<S>(dwa_ctx*, void*, const void*, int, int);                              \
+  template int unpack5_p<S>(dwa_ctx*, void*, const void*, int, int);                            \
+  template int pack_links_p<S>(dwa_ctx*, void*, const void*);                                   \
+  template int convert_p<S, F64>(dwa_ctx*, void*, const void*, size_t, double);                 \
+  template int convert_p<S, F32>(dwa_ctx*, void*, const void*, size_t, double);                 \
+  template int convert_p<S, BF16>(dwa_ctx*, void*, const void*, size_t, double);
+
+}  // namespace dwa

@@ -98,8 +98,102 @@ bool inverse(const Mat& a, int n, Mat& inv) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// sweep programs
+
+namespace {
+
+struct Stage {
+  int type = 0;
+  double A[kLsPad] = {0}, B[kLsPad] = {0}, C[kLsPad] = {0}, W = 0.0;
+};
+
+Stage scale_stage(const std::vector<double>& d) {
+  Stage st;
+  st.type = ST_SCALE;
+  for (size_t s = 0; s < d.size(); ++s) st.A[s] = d[s];
+  return st;
+}
+
+// a cyclic bidiagonal matrix: lower (entries [s][s-1], corner [0][Ls-1]) or upper
+// (entries [s][s+1], corner [Ls-1][0])
+Stage bidiag_stage(const Mat& M, int n, bool lower) {
+  Stage st;
+  st.type = lower ? ST_LBI : ST_UBI;
+  for (int s = 0; s < n; ++s) {
+    st.A[s] = M[s * n + s];
+    if (lower) st.B[s] = s >= 1 ? M[s * n + (s - 1)] : M[0 * n + (n - 1)];
+    else st.B[s] = s + 1 < n ? M[s * n + (s + 1)] : M[(n - 1) * n + 0];
+  }
+  return st;
+}
+
+// solve with a cyclic bidiagonal matrix.  Lower: y_s = (x_s - e_s y_{s-1}) / d_s with
+// y_{-1} -> corner * y_{Ls-1}; writing y_s = a_s + f_s y_{Ls-1} gives a forward sweep for
+// a_s, the closure y_{Ls-1} = a_{Ls-1} / (1 - f_{Ls-1}) and a second pass.  Upper mirrors
+// it with y_0.
+Stage solve_stage(const Mat& M, int n, bool lower) {
+  Stage st;
+  st.type = lower ? ST_LSOLVE : ST_USOLVE;
+  std::vector<double> d(n), e(n);
+  for (int s = 0; s < n; ++s) {
+    d[s] = M[s * n + s];
+    if (lower) e[s] = s >= 1 ? M[s * n + (s - 1)] : M[0 * n + (n - 1)];
+    else e[s] = s + 1 < n ? M[s * n + (s + 1)] : M[(n - 1) * n + 0];
+  }
+  for (int s = 0; s < n; ++s) {
+    st.A[s] = 1.0 / d[s];
+    st.B[s] = e[s] / d[s];
+  }
+  if (lower) {
+    st.C[0] = -st.B[0];
+    for (int s = 1; s < n; ++s) st.C[s] = -st.B[s] * st.C[s - 1];
+    st.W = 1.0 / (1.0 - st.C[n - 1]);
+  } else {
+    st.C[n - 1] = -st.B[n - 1];
+    for (int s = n - 2; s >= 0; --s) st.C[s] = -st.B[s] * st.C[s + 1];
+    st.W = 1.0 / (1.0 - st.C[0]);
+  }
+  return st;
+}
+
+void apply_stage_host(const Stage& st, int n, std::vector<double>& v) {
+  std::vector<double> x = v;
+  switch (st.type) {
+    case ST_SCALE:
+      for (int s = 0; s < n; ++s) v[s] = st.A[s] * x[s];
+      break;
+    case ST_LBI:
+      for (int s = 0; s < n; ++s) v[s] = st.A[s] * x[s] + st.B[s] * x[(s + n - 1) % n];
+      break;
+    case ST_UBI:
+      for (int s = 0; s < n; ++s) v[s] = st.A[s] * x[s] + st.B[s] * x[(s + 1) % n];
+      break;
+    case ST_LSOLVE: {
+      v[0] = st.A[0] * x[0];
+      for (int s = 1; s < n; ++s) v[s] = st.A[s] * x[s] - st.B[s] * v[s - 1];
+      const double Y = st.W * v[n - 1];
+      for (int s = 0; s < n - 1; ++s) v[s] += st.C[s] * Y;
+      v[n - 1] = Y;
+      break;
+    }
+    case ST_USOLVE: {
+      v[n - 1] = st.A[n - 1] * x[n - 1];
+      for (int s = n - 2; s >= 0; --s) v[s] = st.A[s] * x[s] - st.B[s] * v[s + 1];
+      const double Y = st.W * v[0];
+      for (int s = 1; s < n; ++s) v[s] += st.C[s] * Y;
+      v[0] = Y;
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+}  // namespace
+
 bool build_smatrices(int Ls, double M5, double m, double alpha, const double* b, const double* c,
-                     std::vector<double>& out, std::string& err) {
+                     std::vector<double>& out, std::string& err, SweepTables* sweeps) {
   const int n = Ls;
   // chirality 0 = P+, 1 = P-
   Mat B[2], C[2], G[2], Ginv[2];
@@ -171,6 +265,69 @@ bool build_smatrices(int Ls, double M5, double m, double alpha, const double* b,
     put(MIX_G_BT_G5, ch, GBTg5);
     put(MIX_IINV, ch, I1inv);
     put(MIX_I_ALPHA, ch, mul(I1, G[ch], n));
+
+    if (sweeps) {
+      // P+ (ch 0): B and I_1 are lower cyclic bidiagonal; P- (ch 1): upper
+      const bool low = ch == 0;
+      std::vector<double> g(n), ginv(n), sg(n), sginv(n);
+      for (int s = 0; s < n; ++s) {
+        g[s] = G[ch][s * n + s];
+        ginv[s] = 1.0 / g[s];
+        sg[s] = g5 * g[s];
+        sginv[s] = g5 * ginv[s];
+      }
+      const Mat IT = transpose(I1, n);
+      std::vector<std::vector<Stage>> prog(MIX_COUNT);
+      prog[MIX_BG] = {scale_stage(g), bidiag_stage(B[ch], n, low)};
+      prog[MIX_N] = {solve_stage(I1, n, low), bidiag_stage(B[ch], n, low)};
+      prog[MIX_GINV_IINV] = {solve_stage(I1, n, low), scale_stage(ginv)};
+      prog[MIX_G5_IINVT_GINV] = {scale_stage(sginv), solve_stage(IT, n, !low)};
+      prog[MIX_NT] = {bidiag_stage(BT, n, !low), solve_stage(IT, n, !low)};
+      prog[MIX_G_BT_G5] = {bidiag_stage(BT, n, !low), scale_stage(sg)};
+      prog[MIX_IINV] = {solve_stage(I1, n, low)};
+      prog[MIX_I_ALPHA] = {scale_stage(g), bidiag_stage(I1, n, low)};
+      if (ch == 0) {
+        sweeps->meta.assign(size_t(MIX_COUNT) * 2 * 4, 0);
+        sweeps->coef.assign(size_t(MIX_COUNT) * 2 * kMaxStages * 4 * kLsPad, 0.0);
+      }
+      // check each program against its dense matrix on a few fixed vectors
+      for (int kind = 0; kind < MIX_COUNT; ++kind) {
+        const double* dense = &out[(size_t(kind) * 2 + ch) * n * n];
+        bool ok = true;
+        for (int trial = 0; trial < 3 && ok; ++trial) {
+          std::vector<double> x(n), y(n, 0.0);
+          for (int s = 0; s < n; ++s) x[s] = std::sin(1.7 * (s + 1) + 0.9 * trial) + 0.3;
+          for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) y[i] += dense[i * n + j] * x[j];
+          std::vector<double> v = x;
+          for (const Stage& stg : prog[kind]) apply_stage_host(stg, n, v);
+          double num = 0.0, den = 0.0;
+          for (int s = 0; s < n; ++s) {
+            num += (v[s] - y[s]) * (v[s] - y[s]);
+            den += y[s] * y[s];
+          }
+          ok = std::isfinite(num) && num <= 1e-24 * (den > 0 ? den : 1.0);
+        }
+        int* meta = &sweeps->meta[(size_t(kind) * 2 + ch) * 4];
+        if (!ok) {  // dense fallback
+          meta[0] = 1;
+          meta[1] = ST_DENSE;
+          continue;
+        }
+        meta[0] = (int)prog[kind].size();
+        for (size_t st = 0; st < prog[kind].size(); ++st) {
+          const Stage& stg = prog[kind][st];
+          meta[1 + st] = stg.type;
+          double* cf = &sweeps->coef[((size_t(kind) * 2 + ch) * kMaxStages + st) * 4 * kLsPad];
+          for (int s = 0; s < kLsPad; ++s) {
+            cf[0 * kLsPad + s] = stg.A[s];
+            cf[1 * kLsPad + s] = stg.B[s];
+            cf[2 * kLsPad + s] = stg.C[s];
+          }
+          cf[3 * kLsPad] = stg.W;
+        }
+      }
+    }
   }
   return true;
 }

@@ -84,6 +84,7 @@ def lib():
         "dwa_apply_Dw": (c_int, [P, P, P, c_int]),
         "dwa_apply_Dbb": (c_int, [P, c_int, P, P]),
         "dwa_apply_Dbb_dag": (c_int, [P, c_int, P, P]),
+        "dwa_apply_hop": (c_int, [P, c_int, c_int, c_int, P, P]),
         "dwa_cgne_solve": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats)]),
         "dwa_propagator": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats), P]),
         "dwa_strerror": (ctypes.c_char_p, [c_int]),
@@ -240,6 +241,16 @@ class Context:
 
     def apply_Dbb_dag(self, inp, prec="f64", out=None):
         return self.apply_Dbb(inp, prec, out, dagger=True)
+
+    def apply_hop(self, inp, parity_out, kind="N", prec="f64", out=None):
+        """One fused hop launch: out = M_kind (H inp) from parity 1 - parity_out."""
+        p = self._check_half(inp, prec)
+        if out is None:
+            out = self.half_field(prec, zero=False)
+        self._check_half(out, prec)
+        k = MIX_KINDS[kind] if isinstance(kind, str) else int(kind)
+        check(lib().dwa_apply_hop(self._h, p, int(parity_out), k, _ptr(out), _ptr(inp)))
+        return out
 
     # -- solvers --------------------------------------------------------------
     @staticmethod
