@@ -7,7 +7,7 @@ M5 = -1.8 (Wilson diagonal 2.2), m = 0.01, b = 1.5, c = 0.5, Z2-noise source.
 
 One step is one full pass of the hot path: source rho = D_1(1) P b, Schur
 right-hand side, CG on the normal equations of D_bb to a 1e-10 relative residual
-(mixed precision: inner CGLS with low-precision storage, FP64 defect correction),
+(mixed precision: CGLS with low-precision storage and FP64 reliable updates),
 reconstruction and extraction of y_1.  Inputs are resident in HBM before the timed
 region.  The JSON line reports the mixed-precision time to 1e-10 as `value`, the
 FP64 time beside it, D_bb bandwidth per precision, the roofline of the fused hop
@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--workload", default="c3_16x16x16x32_ls16")
     ap.add_argument("--inner", default="bf16", choices=["f32", "bf16"])
     ap.add_argument("--delta", type=float, default=None)
+    ap.add_argument("--mixed-mode", default="reliable", choices=["reliable", "defect"])
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--check-every", type=int, default=10)
@@ -151,7 +152,8 @@ def main():
 
     # --- mixed-precision steps (timed) ------------------------------------------------
     delta = args.delta if args.delta is not None else (0.3 if args.inner == "bf16" else 0.05)
-    kw = dict(tol=args.tol, inner_prec=args.inner, delta=delta, check_every=args.check_every)
+    kw = dict(tol=args.tol, inner_prec=args.inner, delta=delta, check_every=args.check_every,
+              mixed_mode=args.mixed_mode)
     for i in range(args.warmup):
         log(f"warmup {i}")
         ctx.propagator(eta_d, **kw)
@@ -178,6 +180,7 @@ def main():
         cpu = cpu_baseline(U, dims, Ls, w, args.alpha, fp64)
 
     dom = kern[args.inner]
+    dom_name = f"dwa::hop_mix_kernel<dwa::{args.inner.upper()}, 16, {Ls}, 0, 2, false>"
     roofline = {
         "bound": "hbm",
         "kernel": f"hop_mix_kernel<{args.inner.upper()},16,16,0> (fused Wilson hop + N mix)",
@@ -185,7 +188,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(dom["hop_gbs"] / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dom_name),
         "bytes_per_launch": 2 * S[args.inner] + L[args.inner],
     }
     result = {
@@ -203,7 +206,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{dims[0]}^3x{dims[3]} Ls={Ls} m={w['m']} alpha={args.alpha} "
                                f"M5={w['M5']} b={w['b']} c={w['c']} Z2 source, tol {args.tol}",
-                   "plaquette": round(plaq, 6), "inner": args.inner, "delta": delta},
+                   "plaquette": round(plaq, 6), "inner": args.inner, "delta": delta,
+                   "mixed_mode": args.mixed_mode},
         "mixed": {"time_s": round(mixed_s, 4), "iters": stats[-1]["iters"],
                   "outer": stats[-1]["outer"], "rel_resid": stats[-1]["rel_resid"],
                   "y1_rel_diff_vs_fp64": y_err},
@@ -215,6 +219,24 @@ def main():
     }
     print(json.dumps(result), flush=True)
     ctx.close()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
+    the summary was taken on a different kernel source than the one built here."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "paper_1501_04950_amd", "csrc", "kcommon.h")
+    prof = os.path.join(here, "profiles", "hop_mix_kernel_16x16x16x32_ls16_traffic.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        for line in open(prof):
+            f = line.split()
+            if f[:1] == ["traffic_bytes_per_launch"] and " ".join(f[1:-3]) == kernel:
+                return float(f[-3]) if f[-1] == sha else None
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(U, dims, Ls, w, alpha, fp64):

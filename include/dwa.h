@@ -89,13 +89,18 @@ typedef struct {
  *   tol          stop when |phi' - D_bb x| / |phi'| <= tol (recursive residual of CGLS,
  *                confirmed by an FP64 recomputation at the end)
  *   maxiter      cap on CG iterations (inner iterations summed for mixed precision)
- *   inner_prec   DWA_F64: plain FP64 CGLS.  DWA_F32 / DWA_BF16: inner CGLS with fields
- *                stored in that precision and FP32 arithmetic, inside an FP64 outer loop
- *                with true-residual recomputation and reliable updates
- *   delta        reliable-update trigger for mixed precision: the FP64 residual is
- *                recomputed when the inner residual has fallen by this factor (e.g. 0.1)
+ *   inner_prec   DWA_F64: plain FP64 CGLS.  DWA_F32 / DWA_BF16: CGLS with fields stored
+ *                in that precision and FP32 arithmetic (BF16 keeps its accumulated
+ *                solution in FP32), inside an FP64 loop that recomputes the true residual
+ *   delta        mixed precision: the FP64 residual is recomputed when the low-precision
+ *                residual has fallen by this factor since the last recomputation (e.g. 0.3)
  *   check_every  iterations between convergence reads on the host (>= 1)
- *   warm_start   non-zero: start from the x passed in instead of 0 */
+ *   warm_start   non-zero: start from the x passed in instead of 0
+ *   mixed_mode   mixed precision only.  DWA_MIXED_RELIABLE (0): one low-precision CGLS
+ *                keeps its search direction across FP64 residual recomputations
+ *                (reliable updates).  DWA_MIXED_DEFECT (1): defect correction, a fresh
+ *                low-precision CGLS per FP64 residual. */
+enum { DWA_MIXED_RELIABLE = 0, DWA_MIXED_DEFECT = 1 };
 typedef struct {
   double tol;
   int maxiter;
@@ -103,6 +108,7 @@ typedef struct {
   double delta;
   int check_every;
   int warm_start;
+  int mixed_mode;
 } dwa_solve_opts;
 
 typedef struct {

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -55,6 +56,11 @@ void** low_pool(dwa_ctx* ctx, int prec) {
   if (prec == DWA_F32) return ctx->w32;
   if (prec == DWA_BF16) return ctx->w16;
   return ctx->w64;
+}
+
+// buffer for the solution accumulated by a low-precision CGLS (FP32 for BF16 storage)
+void* xacc_buf(dwa_ctx* ctx, int prec) {
+  return prec == DWA_BF16 ? ctx->w32[L_X] : low_pool(ctx, prec)[L_X];
 }
 
 double* bank(dwa_ctx* ctx, int i) { return ctx->d_partials + size_t(i) * ctx->partials_per_bank; }
@@ -114,7 +120,8 @@ int host_norm2(dwa_ctx* ctx, int prec, const void* v, double* out) {
 }
 
 // CGLS on D_bb of precision prec with the workspace pool of that precision.
-// x (in/out) and rhs are fields of precision prec.  Stops when the recursive
+// rhs is a field of precision prec, x one of precision xacc_prec(prec); a warm start
+// (x as given) is supported for FP64 only.  Stops when the recursive
 // residual satisfies |r|^2 <= tol^2 |rhs|^2 or after maxiter iterations.
 struct CgResult {
   int iters = 0;
@@ -140,13 +147,17 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
   int nbA = 0, nbB = 0;
   if (check_every < 1) check_every = 1;
 
+  if (warm && !p64) {
+    set_error("warm-started CGLS needs FP64 storage");
+    return DWA_EINVAL;
+  }
   if (warm) {
     DWA_TRY(apply_dbb(ctx, prec, q, x, u, t));
     DWA_TRY(launch_axpby(ctx, prec, r, 1.0, rhs, 0.0, n));
     DWA_TRY(launch_axpby(ctx, prec, r, -1.0, q, 1.0, n));
     res->n_dbb += 1;
   } else {
-    DWA_TRY(launch_zero(ctx, prec, x, n));
+    DWA_TRY(launch_zero(ctx, xacc_prec(prec), x, n));
     DWA_TRY(launch_axpby(ctx, prec, r, 1.0, rhs, 0.0, n));
   }
   // z = D_bb^dag r, gamma = |z|^2, |rhs|^2
@@ -258,7 +269,7 @@ int mixed_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_sol
     const double need = 0.5 * o->tol / rel;
     if (need > inner_tol) inner_tol = need;
     CgResult cr;
-    DWA_TRY(cgls(ctx, inner, L[L_X], L[L_OPB], false, inner_tol, o->maxiter - total,
+    DWA_TRY(cgls(ctx, inner, xacc_buf(ctx, inner), L[L_OPB], false, inner_tol, o->maxiter - total,
                  o->check_every, &cr));
     total += cr.iters;
     ndbb += cr.n_dbb;
@@ -267,7 +278,7 @@ int mixed_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_sol
       break;
     }
     // x += |r| e  (FP64 accumulate)
-    DWA_TRY(launch_convert(ctx, DWA_F64, W[W_OPB], inner, L[L_X], n, rnorm));
+    DWA_TRY(launch_convert(ctx, DWA_F64, W[W_OPB], xacc_prec(inner), xacc_buf(ctx, inner), n, rnorm));
     DWA_TRY(launch_axpby(ctx, DWA_F64, x, 1.0, W[W_OPB], 1.0, n));
     DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
     ndbb += 1;
@@ -283,6 +294,149 @@ int mixed_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_sol
     prev_rel = rel;
   }
   st->iters = total;
+  st->outer = outer;
+  st->converged = rel <= o->tol;
+  st->rel_resid = rel;
+  st->n_Dbb = ndbb;
+  return status;
+}
+
+// Mixed precision with reliable updates.  One CGLS runs in the low storage precision
+// (FP32 or BF16, FP32 arithmetic) and keeps its search direction p for the whole solve.
+// Its recursive residual r_l drifts from the true one at the level of the storage
+// rounding, so whenever |r_l| has fallen by delta since the last update the low
+// correction x_l is added into the FP64 solution, the true residual rhs - D_bb x is
+// recomputed in FP64 and replaces r_l, and CGLS continues from there (z = D_bb^dag r,
+// beta = |z|^2 / gamma).  The solve stops on the FP64 residual.
+int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_solve_opts* o,
+                   dwa_solve_stats* st) {
+  void** W = ctx->w64;
+  void** Lw = low_pool(ctx, inner);
+  void* r = Lw[L_R];
+  void* p = Lw[L_P];
+  void* z = Lw[L_Z];
+  void* q = Lw[L_Q];
+  void* w = Lw[L_W];
+  void* u = Lw[L_U];
+  void* t = Lw[L_T];
+  void* xl = xacc_buf(ctx, inner);
+  const int xprec = xacc_prec(inner);
+  const size_t n = field_elems(ctx);
+  DevScalars* sc = ctx->d_scal;
+  int nbA = 0, nbB = 0;
+  const int check_every = o->check_every < 1 ? 1 : o->check_every;
+  const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
+
+  double b2 = 0.0;
+  DWA_TRY(host_norm2(ctx, DWA_F64, rhs, &b2));
+  const double bnorm = std::sqrt(b2);
+  if (!o->warm_start) DWA_TRY(launch_zero(ctx, DWA_F64, x, n));
+  if (bnorm == 0.0) {
+    st->converged = 1;
+    st->rel_resid = 0.0;
+    return DWA_OK;
+  }
+  long long ndbb = 0;
+  int outer = 0;
+  double rel = 1.0;
+  if (o->warm_start) {
+    DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
+    ndbb += 1;
+  } else {
+    DWA_TRY(launch_axpby(ctx, DWA_F64, W[W_RES], 1.0, rhs, 0.0, n));
+  }
+  if (rel <= o->tol) {
+    st->converged = 1;
+    st->rel_resid = rel;
+    return DWA_OK;
+  }
+  // low-precision state, scaled so the residual starts at unit norm
+  double scale = rel * bnorm;  // FP64 residual norm at the last update
+  DWA_TRY(launch_convert(ctx, inner, r, DWA_F64, W[W_RES], n, 1.0 / scale));
+  DWA_TRY(launch_zero(ctx, xprec, xl, n));
+  DWA_TRY(launch_smix(ctx, inner, MIX_G5_IINVT_GINV, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  DWA_TRY(dbbdag_from_premix(ctx, inner, z, r, w, t, bank(ctx, 0), &nbA));
+  DWA_TRY(launch_norm2(ctx, inner, r, n, bank(ctx, 1), &nbB));
+  DWA_TRY(launch_cg_finalize(ctx, 2, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
+  DWA_TRY(launch_axpby(ctx, inner, p, 1.0, z, 0.0, n));
+  DWA_TRY(launch_smix(ctx, inner, MIX_BG, u, p, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  ndbb += 1;
+
+  int k = 0, status = DWA_ENOCONV, stall = 0;
+  const bool trace = std::getenv("DWA_TRACE_SOLVE") != nullptr;
+  double rmax = 1.0;  // |r_l| (scaled units) at the last update
+  double last_rel = rel;
+  while (k < o->maxiter) {
+    // q = D_bb p ; a ; x_l += a p ; r_l -= a q ; |r_l|^2 ; w = g5 I^-T G^-1 r_l
+    DWA_TRY(dbb_from_premix(ctx, inner, q, p, u, t, bank(ctx, 0), &nbA));
+    DWA_TRY(launch_cg_finalize(ctx, 0, sc, bank(ctx, 0), nbA, nullptr, 0));
+    DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB));
+    DWA_TRY(launch_cg_finalize(ctx, 4, sc, bank(ctx, 1), nbB, nullptr, 0));
+    ndbb += 1;
+    ++k;
+    bool update = false, done = false;
+    if (k % check_every == 0 || k >= o->maxiter) {
+      DWA_TRY(read_scalars(ctx));
+      const DevScalars& h = *ctx->h_scal;
+      if (h.flags) {
+        if (trace)
+          std::fprintf(stderr, "[dwa] breakdown at k=%d: gamma=%.3e qq=%.3e zz=%.3e rr=%.3e flags=%d\n",
+                       k, h.gamma, h.qq, h.zz, h.rr, h.flags);
+        status = DWA_EBREAKDOWN;
+        break;
+      }
+      const double rl = std::sqrt(h.rr);  // scaled units
+      // predicted relative residual of the FP64 problem
+      const double pred = rl * scale / bnorm;
+      if (trace)
+        std::fprintf(stderr, "[dwa] k=%d |r_l|=%.3e pred=%.3e gamma=%.3e a=%.3e beta=%.3e qq=%.3e flags=%d\n",
+                     k, rl, pred, h.gamma, h.a, h.beta, h.qq, h.flags);
+      if (rl <= delta * rmax || pred <= 0.5 * o->tol || k >= o->maxiter) update = true;
+    }
+    if (update) {
+      // x += scale * x_l (FP64), x_l = 0; true residual; r_l = r / |r|
+      DWA_TRY(launch_convert(ctx, DWA_F64, W[W_OPB], xprec, xl, n, scale));
+      DWA_TRY(launch_axpby(ctx, DWA_F64, x, 1.0, W[W_OPB], 1.0, n));
+      DWA_TRY(launch_zero(ctx, xprec, xl, n));
+      DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
+      ndbb += 1;
+      ++outer;
+      if (trace) std::fprintf(stderr, "[dwa] update %d at k=%d: true rel %.3e\n", outer, k, rel);
+      if (rel <= o->tol) {
+        status = DWA_OK;
+        done = true;
+      } else {
+        if (!(rel < 0.9 * last_rel)) {
+          if (++stall >= 3) {
+            status = DWA_ENOCONV;
+            break;
+          }
+        } else {
+          stall = 0;
+        }
+        last_rel = rel;
+        // the new residual is stored at unit norm: rescale the CGLS state (p by f,
+        // gamma = |z|^2 by f^2) so the recurrence continues in the new units
+        const double new_scale = rel * bnorm;
+        const double f = scale / new_scale;
+        DWA_TRY(launch_axpby(ctx, inner, p, f, p, 0.0, n));
+        DWA_TRY(launch_scale_gamma(ctx, sc, f * f));
+        scale = new_scale;
+        DWA_TRY(launch_convert(ctx, inner, r, DWA_F64, W[W_RES], n, 1.0 / scale));
+        DWA_TRY(launch_smix(ctx, inner, MIX_G5_IINVT_GINV, w, r, nullptr, 0.0, ctx->Ls, nullptr,
+                            nullptr));
+        DWA_TRY(launch_norm2(ctx, inner, r, n, bank(ctx, 1), &nbB));
+        rmax = 1.0;
+      }
+    }
+    if (done) break;
+    // z = D_bb^dag r_l ; beta = |z|^2 / gamma ; p = z + beta p ; u = B G p
+    DWA_TRY(dbbdag_from_premix(ctx, inner, z, r, w, t, bank(ctx, 0), &nbA));
+    DWA_TRY(launch_cg_finalize(ctx, 1, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
+    DWA_TRY(launch_cg_update2(ctx, inner, p, u, z, sc));
+    ndbb += 1;
+  }
+  st->iters = k;
   st->outer = outer;
   st->converged = rel <= o->tol;
   st->rel_resid = rel;
@@ -606,6 +760,8 @@ int dwa_cgne_solve(dwa_ctx* ctx, void* x, const void* rhs, const dwa_solve_opts*
   if (!x || !rhs || !o) return einval("null argument");
   if (!(o->tol >= 0.0) || o->maxiter < 0) return einval("bad tolerance or maxiter");
   if (!valid_prec(o->inner_prec)) return einval("bad inner precision");
+  if (o->mixed_mode != DWA_MIXED_RELIABLE && o->mixed_mode != DWA_MIXED_DEFECT)
+    return einval("bad mixed_mode");
   if (x == rhs) return einval("x and rhs must not overlap");
   dwa_solve_stats st{};
   const auto t0 = std::chrono::steady_clock::now();
@@ -625,7 +781,8 @@ int dwa_cgne_solve(dwa_ctx* ctx, void* x, const void* rhs, const dwa_solve_opts*
     if (cr.breakdown) status = DWA_EBREAKDOWN;
     else if (!cr.converged) status = DWA_ENOCONV;
   } else {
-    status = mixed_solve(ctx, o->inner_prec, x, rhs, o, &st);
+    status = o->mixed_mode == DWA_MIXED_DEFECT ? mixed_solve(ctx, o->inner_prec, x, rhs, o, &st)
+                                               : reliable_solve(ctx, o->inner_prec, x, rhs, o, &st);
     if (status != DWA_OK && status != DWA_ENOCONV && status != DWA_EBREAKDOWN) return status;
   }
   DWA_HIP(hipStreamSynchronize(ctx->stream), "solve sync");

@@ -70,6 +70,13 @@ struct BF16 {  // bf16 real part in the low half, bf16 imaginary part in the hig
   static constexpr int prec = DWA_BF16;
 };
 
+// Storage of the solution accumulated by a low-precision CGLS: BF16 keeps only 8
+// mantissa bits, too few to sum hundreds of small corrections, so its solution is
+// held in FP32 (the operator fields stay BF16).
+template <typename S> struct XAcc { using type = S; };
+template <> struct XAcc<BF16> { using type = F32; };
+inline int xacc_prec(int prec) { return prec == DWA_BF16 ? DWA_F32 : prec; }
+
 __host__ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
   if ((u & 0x7f800000u) == 0x7f800000u) {  // inf or nan: keep, force a quiet nan payload
@@ -262,13 +269,15 @@ int launch_source(dwa_ctx* ctx, void* chi_b, void* chi_r, void* aux_b, void* aux
 int launch_extract(dwa_ctx* ctx, void* y1, const void* psi_b, const void* psi_r);
 int launch_check_finite(dwa_ctx* ctx, const void* canon, size_t ncomplex, int* d_flag);
 
-// CGLS building blocks (templated on precision inside kernels.hip)
+// CGLS building blocks (templated on precision inside kernels.hip).  In update1, x
+// has storage xacc_prec(prec); the other fields have storage prec.
 int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
                       const void* q, const DevScalars* s, double* partials, int* nblocks);
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
                       const DevScalars* s);
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* partials_a, int na,
                        const double* partials_b, int nb);
+int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f);
 
 // per-precision launchers (kcommon.h), instantiated in kernels_{f64,f32,bf16}.hip
 template <typename S> int launch_hop_p(dwa_ctx*, const HopOp&, int*);

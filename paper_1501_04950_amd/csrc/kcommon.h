@@ -645,7 +645,7 @@ __global__ void __launch_bounds__(256) smix_kernel(typename S::elem* __restrict_
 
 // CGLS update 1: x += a p ; r -= a q ; |r|^2 ; w = (g5 I^-T G^-1) r
 template <typename S, int LS, bool DENSE>
-__global__ void __launch_bounds__(256) cg_update1_kernel(typename S::elem* __restrict__ x,
+__global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type::elem* __restrict__ x,
                                                          typename S::elem* __restrict__ r,
                                                          typename S::elem* __restrict__ w,
                                                          const typename S::elem* __restrict__ p,
@@ -668,10 +668,11 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename S::elem* __res
       for (int j = 0; j < LSM; ++j)
         if (j < Ls) {
           const size_t idx = (size_t(j) * 12 + comp) * Vh + site;
-          cpx<R> xv = ld<S>(x, idx), pv = ld<S>(p, idx), qv = ld<S>(q, idx), rr = ld<S>(r, idx);
+          using SX = typename XAcc<S>::type;
+          cpx<R> xv = ld<SX>(x, idx), pv = ld<S>(p, idx), qv = ld<S>(q, idx), rr = ld<S>(r, idx);
           xv = xv + a * pv;
           rr = rr - a * qv;
-          st<S>(x, idx, xv);
+          st<SX>(x, idx, xv);
           st<S>(r, idx, rr);
           rv[j] = as_stored<S>(rr);  // premix the value as stored
           nrm += (double)norm2(rv[j]);
@@ -978,12 +979,13 @@ template <typename S>
 int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, const void* q,
                      const DevScalars* s, double* partials, int* nblocks) {
   using E = typename S::elem;
+  using EX = typename XAcc<S>::type::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
   const int grid = (int)((6u * Vh + 255) / 256);
   const MixTables T = mix_tables<S>(ctx, MIX_G5_IINVT_GINV);
 #define DWA_U1(LSV, DV)                                                                         \
   hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV>), dim3(grid), dim3(256), 0, ctx->stream,    \
-                     (E*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T, ctx->Ls, Vh, partials)
+                     (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T, ctx->Ls, Vh, partials)
   DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_U1)
 #undef DWA_U1
   if (nblocks) *nblocks = grid;

@@ -230,6 +230,17 @@ int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* pa,
   return hip_fail(hipGetLastError(), "finalize launch");
 }
 
+namespace {
+__global__ void scale_gamma_kernel(DevScalars* s, double f) {
+  if (threadIdx.x == 0) s->gamma *= f;
+}
+}  // namespace
+
+int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f) {
+  hipLaunchKernelGGL(scale_gamma_kernel, dim3(1), dim3(64), 0, ctx->stream, s, f);
+  return hip_fail(hipGetLastError(), "scale gamma launch");
+}
+
 int launch_sum_partials(dwa_ctx* ctx, const double* partials, int n, double* out) {
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(RED_THREADS), 0, ctx->stream, out,
                      partials, n);

@@ -31,6 +31,7 @@ DWA_OK, DWA_EINVAL, DWA_ENOMEM, DWA_EHIP, DWA_ENOCONV, DWA_EBREAKDOWN, DWA_ENAN,
     0, -1, -2, -3, -4, -5, -6, -7)
 DWA_F64, DWA_F32, DWA_BF16 = 0, 1, 2
 PREC = {"f64": DWA_F64, "f32": DWA_F32, "bf16": DWA_BF16}
+MIXED_MODES = {"reliable": 0, "defect": 1}
 
 MIX_KINDS = {"identity": 0, "BG": 1, "N": 2, "Ginv_Iinv": 3, "g5_IinvT_Ginv": 4, "NT": 5,
              "G_BT_g5": 6, "Iinv": 7, "I_alpha": 8}
@@ -44,7 +45,7 @@ class dwa_params(ctypes.Structure):
 
 class dwa_solve_opts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("maxiter", c_int), ("inner_prec", c_int), ("delta", c_double),
-                ("check_every", c_int), ("warm_start", c_int)]
+                ("check_every", c_int), ("warm_start", c_int), ("mixed_mode", c_int)]
 
 
 class dwa_solve_stats(ctypes.Structure):
@@ -255,11 +256,12 @@ class Context:
     # -- solvers --------------------------------------------------------------
     @staticmethod
     def opts(tol=1e-10, maxiter=100000, inner_prec="f64", delta=0.1, check_every=1,
-             warm_start=False):
+             warm_start=False, mixed_mode="reliable"):
         o = dwa_solve_opts()
         o.tol, o.maxiter = float(tol), int(maxiter)
         o.inner_prec = PREC[inner_prec] if isinstance(inner_prec, str) else int(inner_prec)
         o.delta, o.check_every, o.warm_start = float(delta), int(check_every), int(bool(warm_start))
+        o.mixed_mode = MIXED_MODES[mixed_mode] if isinstance(mixed_mode, str) else int(mixed_mode)
         return o
 
     def cgne_solve(self, rhs, x=None, **kw):

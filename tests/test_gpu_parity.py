@@ -240,6 +240,33 @@ def test_mixed_precision_reaches_fp64_accuracy(inner):
     ctx.close()
 
 
+@pytest.mark.parametrize("inner,mode,delta", [("bf16", "reliable", 0.3), ("f32", "reliable", 0.05),
+                                              ("bf16", "defect", 0.3)])
+def test_mixed_precision_bench_workload(inner, mode, delta):
+    """At the 16^3 x 32, Ls = 16 workload the mixed solves reach the FP64 solve's
+    accuracy: true FP64 residual <= 1e-10 and y_1 within kappa * tol of the FP64 y_1.
+    The FP64 D_bb that measures the residual is the one checked against the oracle
+    element by element on the smaller lattices."""
+    dev = gpu()
+    w = synth.WORKLOADS["c3_16x16x16x32_ls16"]
+    say(f"[gpu] bench workload, mixed {inner} {mode} delta={delta}")
+    ctx = dwa.Context(w["dims"], w["Ls"], w["M5"], w["m"], 1.0, w["b"], w["c"])
+    ctx.set_links(torch.from_numpy(synth.workload_links("c3_16x16x16x32_ls16")).to(dev))
+    eta = torch.from_numpy(synth.z2_source(w["dims"], w["seed"] + 100)).to(dev)
+    y64, st64, rc64 = ctx.propagator(eta, tol=1e-10, check_every=10)
+    y, st, rc = ctx.propagator(eta, tol=1e-10, inner_prec=inner, delta=delta, check_every=10,
+                               mixed_mode=mode)
+    say(f"    {inner}/{mode}: iters {st['iters']} outer {st['outer']} resid {st['rel_resid']:.2e}; "
+        f"f64 iters {st64['iters']}")
+    assert rc64 == dwa.DWA_OK and rc == dwa.DWA_OK
+    assert st["rel_resid"] <= 1e-10
+    # both solutions within ~kappa * 1e-10 of the exact one
+    d = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
+    say(f"    |y - y64| / |y64| = {d:.2e}")
+    assert d < 1e-7
+    ctx.close()
+
+
 def test_error_paths():
     cs = case("tiny_2x2x2x2_ls4")
     dev = gpu()
@@ -258,6 +285,9 @@ def test_error_paths():
     eta = torch.from_numpy(synth.gaussian_source(cs.dims, 4)).to(dev)
     y, st, rc = ctx.propagator(eta, tol=1e-14, maxiter=2)
     assert rc == dwa.DWA_ENOCONV and st["iters"] == 2 and not st["converged"]
+    with pytest.raises(dwa.DwaError) as e:
+        ctx.propagator(eta, inner_prec="bf16", mixed_mode=7)
+    assert e.value.status == dwa.DWA_EINVAL
     ctx.close()
 
 
