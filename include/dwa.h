@@ -122,7 +122,9 @@ typedef struct {
 
 /* Create a context for one lattice and parameter set on the current device.
  * Validates: every extent even and >= 2, Ls in [2, 32], alpha != 0, b/c non-null
- * and finite, and that the site-local matrix I of eq.(redblack) is invertible.
+ * and finite, an FP64 half field (Ls * 12 * V/2 * 16 bytes) below 4 GiB (the kernels
+ * use 32-bit byte offsets), and that the site-local matrix I of eq.(redblack) is
+ * invertible.
  * stream is a hipStream_t (NULL = default stream). */
 int dwa_create(dwa_ctx **ctx, const dwa_params *p, void *stream);
 int dwa_destroy(dwa_ctx *ctx);

@@ -487,7 +487,10 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
   for (int s = 0; s < p->Ls; ++s)
     if (!std::isfinite(p->b[s]) || !std::isfinite(p->c[s])) return einval("b, c must be finite");
   const long long V = (long long)p->dims[0] * p->dims[1] * p->dims[2] * p->dims[3];
-  if ((long long)p->Ls * 12 * V > (1LL << 31) - 1) return einval("field too large for 32-bit indexing");
+  // kernels address one FP64 half field (Ls * 12 * V/2 complex numbers of 16 bytes)
+  // with 32-bit byte offsets
+  if ((long long)p->Ls * 12 * (V / 2) * 16 >= (1LL << 32))
+    return einval("lattice too large: an FP64 half field must stay below 4 GiB");
   std::vector<double> mix;
   std::string err;
   SweepTables sweeps;
@@ -557,9 +560,10 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
   // fused-hop traversal: chunks of NS consecutive checkerboard sites, ordered by
   // (t-slab, z, t within the slab, y, x) so that a run of blocks on one XCD touches a
   // compact slab and the t and z neighbours are re-read from L2, not HBM.  Contiguous
-  // ranges of this order go to one XCD (the kernel remaps block ids accordingly).
-  {
-    const int NS = hop_sites_per_block(p->Ls);
+  // ranges of this order go to one XCD (the kernel remaps block ids accordingly).  One
+  // table per block size (8, 16, 32 sites).
+  for (int bi = 0; bi < 3; ++bi) {
+    const int NS = 8 << bi;
     const long long nchunk = (Vh + NS - 1) / NS;
     std::vector<int> order(nchunk);
     for (long long c = 0; c < nchunk; ++c) order[c] = (int)c;
@@ -580,9 +584,9 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
       std::stable_sort(order.begin(), order.end(),
                        [&](int a, int b) { return key[a] < key[b]; });
     }
-    if ((rc = hip_fail(hipMalloc(&ctx->d_blkmap, sizeof(int) * order.size()), "alloc blkmap")))
+    if ((rc = hip_fail(hipMalloc(&ctx->d_blkmap[bi], sizeof(int) * order.size()), "alloc blkmap")))
       return fail(rc);
-    if ((rc = hip_fail(hipMemcpy(ctx->d_blkmap, order.data(), sizeof(int) * order.size(),
+    if ((rc = hip_fail(hipMemcpy(ctx->d_blkmap[bi], order.data(), sizeof(int) * order.size(),
                                  hipMemcpyHostToDevice), "upload blkmap")))
       return fail(rc);
   }
@@ -643,7 +647,7 @@ int dwa_destroy(dwa_ctx* ctx) {
   };
   f(ctx->d_nbr);
   f(ctx->d_cb2lex);
-  f(ctx->d_blkmap);
+  for (auto p : ctx->d_blkmap) f(p);
   f(ctx->d_mix64);
   f(ctx->d_mix32);
   f(ctx->d_sweep_meta);

@@ -111,9 +111,30 @@ template <>
 __device__ __forceinline__ void st<F64>(double2* p, size_t i, cpx<double> v) { p[i] = make_double2(v.re, v.im); }
 template <>
 __device__ __forceinline__ void st<F32>(float2* p, size_t i, cpx<float> v) { p[i] = make_float2(v.re, v.im); }
+// Device rounding of two floats to a packed bf16 pair (real part in the low half),
+// round-to-nearest-even by the gfx950 conversion instruction.  It agrees with
+// f32_to_bf16_rne on every finite input.
+__device__ __forceinline__ uint32_t pack_bf16x2(float re, float im) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+  const f2v f = {re, im};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, b2v));
+}
 template <>
 __device__ __forceinline__ void st<BF16>(uint32_t* p, size_t i, cpx<float> v) {
-  p[i] = f32_to_bf16_rne(v.re) | (f32_to_bf16_rne(v.im) << 16);
+  p[i] = pack_bf16x2(v.re, v.im);
+}
+
+// Load of element byte_off / sizeof(elem) from a wave-uniform base: the 32-bit
+// per-lane byte offset lets the compiler address through base (scalar registers) +
+// offset (one vector register), with no 64-bit address arithmetic per load.
+template <typename S>
+__device__ __forceinline__ cpx<typename S::real> ldb(const void* base, unsigned byte_off) {
+  return ld<S>(reinterpret_cast<const typename S::elem*>(static_cast<const char*>(base) + byte_off), 0);
+}
+template <typename S>
+__device__ __forceinline__ void stb(void* base, unsigned byte_off, cpx<typename S::real> v) {
+  st<S>(reinterpret_cast<typename S::elem*>(static_cast<char*>(base) + byte_off), 0, v);
 }
 
 inline size_t elem_bytes(int prec) { return prec == DWA_F64 ? 16 : (prec == DWA_F32 ? 8 : 4); }
@@ -206,7 +227,7 @@ struct dwa_ctx {
   // geometry
   int* d_nbr = nullptr;   // [2][8][Vh] neighbour cb index for an output site of parity p
   int* d_cb2lex = nullptr;  // [2][Vh]
-  int* d_blkmap = nullptr;  // fused-hop block -> chunk of sites (traversal order)
+  int* d_blkmap[3] = {nullptr, nullptr, nullptr};  // fused-hop block -> chunk of 8/16/32 sites
   // s-matrices (FP64 and FP32 copies), [MIX_COUNT][2][Ls][Ls]
   double* d_mix64 = nullptr;
   float* d_mix32 = nullptr;
@@ -234,9 +255,15 @@ namespace dwa {
 
 // Sites per block of the fused hop kernel: 16 for the Ls with their own kernels
 // (4, 8, 12, 16), 8 for the generic kernel (Ls <= 32).
-inline int hop_sites_per_block(int Ls) {
-  return (Ls == 4 || Ls == 8 || Ls == 12 || Ls == 16) ? 16 : 8;
+// Sites per block of the fused hop: Ls values with their own kernels run 32 sites
+// (FP32 / BF16: one 128-byte line per colour-spin component and slice) or 16 (FP64,
+// whose LDS tile is twice as large); the generic and dense kernels run 8.
+inline int hop_sites_per_block(int prec, int Ls, bool dense) {
+  if (dense || !(Ls == 4 || Ls == 8 || Ls == 12 || Ls == 16)) return 8;
+  return prec == DWA_F64 ? 16 : 32;
 }
+// index of the block traversal table for a given number of sites per block
+inline int blkmap_index(int ns) { return ns == 8 ? 0 : (ns == 16 ? 1 : 2); }
 
 // kernel launchers (kernels.hip)
 struct HopOp {

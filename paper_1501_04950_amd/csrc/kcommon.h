@@ -23,10 +23,73 @@ using RealOf = typename S::real;
 template <typename S>
 __device__ __forceinline__ cpx<RealOf<S>> as_stored(cpx<RealOf<S>> v) {
   if constexpr (S::prec == DWA_BF16) {
-    return cmk<float>(bf16_to_f32(f32_to_bf16_rne(v.re)), bf16_to_f32(f32_to_bf16_rne(v.im)));
+    const uint32_t b = pack_bf16x2(v.re, v.im);
+    return cmk<float>(__uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u));
   } else {
     return v;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Raw buffer access to one half field.  The descriptor (base, size in bytes) sits in
+// scalar registers; a load or store takes a 32-bit lane offset plus a wave-uniform
+// scalar offset, so the twelve colour-spin components of a gather share one vector
+// address and cost no vector arithmetic.  Fields are below 4 GiB (checked when a
+// context is created); reads past the size return zero.
+typedef unsigned dwa_v2u __attribute__((ext_vector_type(2)));
+typedef unsigned dwa_v4u __attribute__((ext_vector_type(4)));
+typedef float dwa_v2f __attribute__((ext_vector_type(2)));
+typedef double dwa_v2d __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  // 0x00020000: the descriptor word 3 of gfx9 raw (untyped, stride 0) buffers
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename S>
+__device__ __forceinline__ cpx<typename S::real> ldbuf(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                       unsigned soff) {
+  if constexpr (S::prec == DWA_F64) {
+    const dwa_v2d d = __builtin_bit_cast(dwa_v2d, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return {d.x, d.y};
+  } else if constexpr (S::prec == DWA_F32) {
+    const dwa_v2f f = __builtin_bit_cast(dwa_v2f, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return {f.x, f.y};
+  } else {
+    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
+                                      cpx<typename S::real> v) {
+  if constexpr (S::prec == DWA_F64) {
+    const dwa_v2d d = {v.re, v.im};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(dwa_v4u, d), r, voff, soff, 0);
+  } else if constexpr (S::prec == DWA_F32) {
+    const dwa_v2f f = {v.re, v.im};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(dwa_v2u, f), r, voff, soff, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(pack_bf16x2(v.re, v.im), r, voff, soff, 0);
+  }
+}
+
+// Complex numbers in LDS as naturally aligned two-element vectors, so that an access
+// is one ds_read/ds_write_b64 (b128 for doubles) whose 16-bit offset field reaches the
+// whole tile.
+template <typename R> struct LdsT;
+template <> struct LdsT<float> { using type = dwa_v2f; };
+template <> struct LdsT<double> { using type = dwa_v2d; };
+template <typename R>
+using lcpx = typename LdsT<R>::type;
+template <typename R>
+__device__ __forceinline__ lcpx<R> to_lds(cpx<R> v) {
+  return lcpx<R>{v.re, v.im};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> from_lds(lcpx<R> v) {
+  return cmk<R>(v.x, v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,11 +440,16 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nblocks) {
 }
 
 
-// One site of H psi with the neighbour indices and links of the block in LDS.
+// One site of H psi with the neighbour offsets and links of the block in LDS.  in is
+// the input field's buffer descriptor, sboff the byte offset of this thread's slice,
+// cstride = Vh * sizeof(elem) the byte stride between colour-spin components, and
+// lnbr[dir * NS + sl] the neighbour's byte offset nb * sizeof(elem).  Every gather is
+// (one lane offset per direction) + (scalar offset of the component).
 template <typename S>
-__device__ __forceinline__ void hop_site_lds(const typename S::elem* __restrict__ ins,
-                                             const unsigned* lnbr, const cpx<RealOf<S>>* llink,
-                                             int sl, int NS, unsigned Vh, cpx<RealOf<S>> acc[12]) {
+__device__ __forceinline__ void hop_site_lds(__amdgpu_buffer_rsrc_t in, unsigned sboff,
+                                             unsigned cstride, const unsigned* lnbr,
+                                             const lcpx<RealOf<S>>* llink, int sl, int NS,
+                                             cpx<RealOf<S>> acc[12]) {
   using R = RealOf<S>;
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = cmk<R>(0, 0);
@@ -391,12 +459,12 @@ __device__ __forceinline__ void hop_site_lds(const typename S::elem* __restrict_
   for (int dir = 0; dir < 8; ++dir) {
     const int mu = dir & 3;
     const bool fwd = dir < 4;
-    const unsigned nb = lnbr[dir * NS + sl];
+    const unsigned off = sboff + lnbr[dir * NS + sl];
     cpx<R> ps[4][3];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int co = 0; co < 3; ++co) ps[sp][co] = ld<S>(ins, (sp * 3 + co) * Vh + nb);
+      for (int co = 0; co < 3; ++co) ps[sp][co] = ldbuf<S>(in, off, unsigned(sp * 3 + co) * cstride);
     cpx<R> h[2][3];
 #pragma unroll
     for (int co = 0; co < 3; ++co) {
@@ -417,7 +485,7 @@ __device__ __forceinline__ void hop_site_lds(const typename S::elem* __restrict_
     }
     cpx<R> u[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = llink[(dir * 9 + k) * NS + sl];
+    for (int k = 0; k < 9; ++k) u[k] = from_lds<R>(llink[(dir * 9 + k) * NS + sl]);
     cpx<R> v[2][3];
 #pragma unroll
     for (int hs = 0; hs < 2; ++hs)
@@ -467,7 +535,7 @@ __host__ __device__ constexpr size_t hop_mix_lds_bytes(int NS, int Ls) {
 // Phase 2 of hop_mix_kernel for one (site, component) of chirality CH: read the Ls
 // values from the tile, apply the fifth-dimension matrix, add the post term, store.
 template <typename S, int NS, int LSM, int MODE, int KIND, int CH, bool DENSE>
-__device__ __forceinline__ double hop_mix_out(const HopDev& a, const cpx<RealOf<S>>* tile,
+__device__ __forceinline__ double hop_mix_out(const HopDev& a, const lcpx<RealOf<S>>* tile,
                                               unsigned site0, int Ls, int lt) {
   using R = RealOf<S>;
   using E = typename S::elem;
@@ -477,19 +545,22 @@ __device__ __forceinline__ double hop_mix_out(const HopDev& a, const cpx<RealOf<
   cpx<R> v[LSM];
 #pragma unroll
   for (int j = 0; j < LSM; ++j)
-    if (j < Ls) v[j] = tile[(j * 12 + comp) * NSP + sl];
+    if (j < Ls) v[j] = from_lds<R>(tile[(j * 12 + comp) * NSP + sl]);
   apply_mix<R, LSM, KIND, CH, DENSE>(v, Ls, a.mix);
   double nrm = 0.0;
   if (site < a.Vh) {
     const R qc = (R)a.post_coef;
+    const unsigned sstride = 12u * a.Vh * unsigned(sizeof(E));  // bytes per slice
+    const unsigned fbytes = unsigned(Ls) * sstride;
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(a.out, fbytes);
+    const unsigned off = (unsigned(comp) * a.Vh + site) * unsigned(sizeof(E));
 #pragma unroll
     for (int i = 0; i < LSM; ++i)
       if (i < Ls) {
         cpx<R> o = v[i];
-        const unsigned idx = (unsigned(i) * 12u + unsigned(comp)) * a.Vh + site;
-        if (MODE == 1) o = o + qc * ld<S>((const E*)a.post, idx);
-        st<S>((E*)a.out, idx, o);
-        nrm += (double)norm2(o);
+        if (MODE == 1) o = o + qc * ldbuf<S>(make_rsrc(a.post, fbytes), off, unsigned(i) * sstride);
+        stbuf<S>(rout, off, unsigned(i) * sstride, o);
+        if constexpr (MODE == 1) nrm += (double)norm2(o);
       }
   }
   return nrm;
@@ -511,7 +582,8 @@ __device__ __forceinline__ double hop_mix_out(const HopDev& a, const cpx<RealOf<
 // LS > 0: Ls is the compile-time LS; LS == 0: runtime Ls <= 32.
 // MODE selects the epilogue at compile time so that each use is its own kernel:
 //   0: out = M H in                 (first hop of D_bb / D_bb^dag)
-//   1: out = M (hop_coef H in) + post_coef post   (second hop, with the x term)
+//   1: out = M (hop_coef H in) + post_coef post   (second hop, with the x term; the
+//      only epilogue that also writes per-block partial sums of |out|^2)
 //   2: out = M (hop_coef H in + pre_coef pre)     (Schur prep and reconstruction)
 template <typename S, int NS, int LS, int MODE, int KIND, bool DENSE>
 __global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a) {
@@ -519,10 +591,10 @@ __global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a
   using E = typename S::elem;
   constexpr int LSM = LS > 0 ? LS : 32;
   constexpr int NSP = NS + 1;
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   const int Ls = LS > 0 ? LS : a.nslices;
-  cpx<R>* tile = reinterpret_cast<cpx<R>*>(smem_raw);
-  cpx<R>* llink = tile;  // phase 0/1 only
+  lcpx<R>* tile = reinterpret_cast<lcpx<R>*>(smem_raw);
+  lcpx<R>* llink = tile;  // phase 0/1 only
   const size_t region = size_t(Ls) * 12 * NSP * sizeof(cpx<R>) > size_t(72) * NS * sizeof(cpx<R>)
                             ? size_t(Ls) * 12 * NSP * sizeof(cpx<R>)
                             : size_t(72) * NS * sizeof(cpx<R>);
@@ -531,45 +603,46 @@ __global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a
   const unsigned site0 = (a.blkmap ? (unsigned)a.blkmap[blk] : blk) * NS;
   const int p = a.parity_out;
   const unsigned Vh = a.Vh;
+  const unsigned cstride = Vh * unsigned(sizeof(E));  // bytes between components
 
-  // phase 0: neighbour indices, then links
-  for (int e = threadIdx.x; e < 8 * NS; e += blockDim.x) {
-    const int dir = e / NS, sl = e % NS;
-    const unsigned site = site0 + sl;
-    lnbr[e] = site < Vh ? (unsigned)a.nbr[(p * 8 + dir) * Vh + site] : 0u;
-  }
+  // phase 0: neighbour byte offsets, then links.  Thread (sl, j) stages rows j,
+  // j + nthreads / NS, ... of site sl (NS is a power of two).
+  const int sl1 = threadIdx.x % NS, j1 = threadIdx.x / NS;
+  const int nj = blockDim.x / NS;
+  const unsigned site1 = site0 + sl1;
+  for (int dir = j1; dir < 8; dir += nj)
+    lnbr[dir * NS + sl1] = site1 < Vh ? (unsigned)a.nbr[(p * 8 + dir) * Vh + site1] * unsigned(sizeof(E)) : 0u;
   __syncthreads();
   {
     const E* L = (const E*)a.links;
-    for (int e = threadIdx.x; e < 72 * NS; e += blockDim.x) {
-      const int sl = e % NS, r = e / NS, k = r % 9, dir = r / 9, mu = dir & 3;
-      const unsigned site = site0 + sl;
+    for (int r = j1; r < 72; r += nj) {
+      const int dir = r / 9, k = r - 9 * dir, mu = dir & 3;
       cpx<R> v = cmk<R>(0, 0);
-      if (site < Vh) {
+      if (site1 < Vh) {
         const bool fwd = dir < 4;
-        const unsigned lsite = fwd ? site : lnbr[dir * NS + sl];
+        const unsigned lsite = fwd ? site1 : lnbr[dir * NS + sl1] / unsigned(sizeof(E));
         const int lpar = fwd ? p : 1 - p;
         v = ld<S>(L, ((lpar * 4 + mu) * 9 + k) * Vh + lsite);
       }
-      llink[(dir * 9 + k) * NS + sl] = v;
+      llink[r * NS + sl1] = to_lds<R>(v);
     }
   }
   __syncthreads();
 
-  // phase 1: hop
-  const int sl1 = threadIdx.x % NS, s1 = threadIdx.x / NS;
-  const unsigned site1 = site0 + sl1;
+  // phase 1: hop, thread (site sl1, slice s1)
+  const int s1 = j1;
   cpx<R> acc[12];
   const bool act1 = s1 < Ls && site1 < Vh;
   if (act1) {
-    hop_site_lds<S>((const E*)a.in + size_t(s1) * 12 * Vh, lnbr, llink, sl1, NS, Vh, acc);
+    const unsigned sboff = unsigned(s1) * 12u * cstride;
+    hop_site_lds<S>(make_rsrc(a.in, unsigned(Ls) * 12u * cstride), sboff, cstride, lnbr, llink, sl1, NS, acc);
     if (MODE != 0) {
       const R hc = (R)a.hop_coef, pc = (R)a.pre_coef;
-      const unsigned base = unsigned(s1) * 12u * Vh + site1;
+      const unsigned off = sboff + site1 * unsigned(sizeof(E));
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         cpx<R> o = hc * acc[k];
-        if (MODE == 2) o = o + pc * ld<S>((const E*)a.pre, base + unsigned(k) * Vh);
+        if (MODE == 2) o = o + pc * ldbuf<S>(make_rsrc(a.pre, unsigned(Ls) * 12u * cstride), off, unsigned(k) * cstride);
         acc[k] = o;
       }
     }
@@ -580,7 +653,7 @@ __global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a
   __syncthreads();  // every thread is done with the links
   if (s1 < Ls) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) tile[(s1 * 12 + k) * NSP + sl1] = acc[k];
+    for (int k = 0; k < 12; ++k) tile[(s1 * 12 + k) * NSP + sl1] = to_lds<R>(acc[k]);
   }
   __syncthreads();
 
@@ -597,7 +670,7 @@ __global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a
     else
       nrm += hop_mix_out<S, NS, LSM, MODE, KIND, 1, DENSE>(a, tile, site0, Ls, lt);
   }
-  if (a.partials) block_sum_to(nrm, &a.partials[blockIdx.x]);
+  if (MODE == 1 && a.partials) block_sum_to(nrm, &a.partials[blockIdx.x]);
 }
 
 // Site-local kernels run one thread per (site, colour-spin component of one chirality)
@@ -876,7 +949,7 @@ template <typename S, int MODE, int KIND>
 void launch_hop_mix_mk(dwa_ctx* ctx, const HopDev& a, unsigned grid, dim3 block, size_t shm) {
 #define DWA_HOPMIX(LSV, DV)                                                                   \
   {                                                                                           \
-    constexpr int NSV = LSV > 0 ? 16 : 8;                                                     \
+    constexpr int NSV = LSV > 0 ? (S::prec == DWA_F64 ? 16 : 32) : 8;                         \
     hipLaunchKernelGGL((hop_mix_kernel<S, NSV, LSV, MODE, KIND, DV>), dim3(grid), block, shm, \
                        ctx->stream, a);                                                       \
   }
@@ -895,7 +968,8 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
   a.nbr = ctx->d_nbr;
   a.mix = mix_tables<S>(ctx, op.mix);
   a.partials = op.partials;
-  a.blkmap = ctx->d_blkmap;
+  const int NS = hop_sites_per_block(S::prec, op.nslices, ctx->dense_mix);
+  a.blkmap = ctx->d_blkmap[blkmap_index(NS)];
   a.hop_coef = op.hop_coef;
   a.pre_coef = op.pre_coef;
   a.post_coef = op.post_coef;
@@ -913,7 +987,6 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
     set_error("fused hop runs on the context's Ls slices");
     return DWA_EINVAL;
   }
-  const int NS = ctx->dense_mix ? 8 : hop_sites_per_block(Ls);
   const unsigned grid = (unsigned)((ctx->Vh + NS - 1) / NS);
   const size_t shm = hop_mix_lds_bytes<RealOf<S>>(NS, Ls);
   const dim3 block(NS * Ls);
@@ -924,6 +997,10 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
   }
   if (mode == 0 && op.hop_coef != 1.0) {
     set_error("plain fused hop takes hop_coef = 1");
+    return DWA_EINVAL;
+  }
+  if (op.partials && mode != 1) {
+    set_error("fused hop: output norms are computed only with a post term");
     return DWA_EINVAL;
   }
   if (mode == 0 && op.mix == MIX_N) launch_hop_mix_mk<S, 0, MIX_N>(ctx, a, grid, block, shm);

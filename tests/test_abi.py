@@ -41,7 +41,9 @@ def _create(**kw):
 
 @pytest.mark.parametrize("kw", [dict(dims=(5, 4, 4, 4)), dict(dims=(4, 4, 3, 4)),
                                 dict(dims=(0, 4, 4, 4)), dict(Ls=1), dict(Ls=33),
-                                dict(alpha=0.0), dict(alpha=float("nan")), dict(m=float("inf"))])
+                                dict(alpha=0.0), dict(alpha=float("nan")), dict(m=float("inf")),
+                                # FP64 half field of 16 * 12 * 2^21 * 16 B = 6 GiB > 4 GiB
+                                dict(dims=(64, 64, 32, 32), Ls=16)])
 def test_create_rejects_bad_arguments(kw):
     assert _create(**kw) == dwa.DWA_EINVAL
     assert dwa.lib().dwa_last_error().decode()
