@@ -567,10 +567,14 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
     const long long nchunk = (Vh + NS - 1) / NS;
     std::vector<int> order(nchunk);
     for (long long c = 0; c < nchunk; ++c) order[c] = (int)c;
+    // DWA_HOP_ORDER (tuning): "slab" (default), "lex" (checkerboard order), or
+    // "zdom" (XCD k owns z-planes [k Lz/8, (k+1) Lz/8) and walks them t-major)
     const char* env = std::getenv("DWA_HOP_ORDER");
-    const bool lexical = env && std::string(env) == "lex";
-    if (!lexical) {
+    const std::string order_kind = env ? std::string(env) : std::string("slab");
+    if (order_kind != "lex") {
+      const bool zdom = order_kind == "zdom" && Lz % 8 == 0;
       const int ts = Lt >= 16 ? Lt / 8 : 1;
+      const int zpd = Lz / 8;
       std::vector<long long> key(nchunk);
       for (long long c = 0; c < nchunk; ++c) {
         long long lex = cb2lex[c * NS];
@@ -579,7 +583,8 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
         const long long y = r % Ly; r /= Ly;
         const long long z = r % Lz;
         const long long t = r / Lz;
-        key[c] = ((((t / ts) * Lz + z) * ts + (t % ts)) * Ly + y) * Lx + x;
+        key[c] = zdom ? ((((z / zpd) * Lt + t) * zpd + z % zpd) * Ly + y) * Lx + x
+                      : ((((t / ts) * Lz + z) * ts + (t % ts)) * Ly + y) * Lx + x;
       }
       std::stable_sort(order.begin(), order.end(),
                        [&](int a, int b) { return key[a] < key[b]; });
@@ -616,6 +621,8 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
     for (size_t k = 0; k < sweeps.meta.size(); k += 4)
       if (sweeps.meta[k + 1] == ST_DENSE) ctx->dense_mix = true;
     if (std::getenv("DWA_DENSE_MIX")) ctx->dense_mix = true;
+    if (const char* e = std::getenv("DWA_HOP_MIN_LDS_KB"))
+      ctx->hop_min_lds = std::min<size_t>(size_t(std::max(0, std::atoi(e))) * 1024, 160 * 1024);
   }
   // links and workspace
   const size_t n = field_elems(ctx);

@@ -236,6 +236,7 @@ struct dwa_ctx {
   float* d_sweep32 = nullptr;
   std::vector<int> sweep_meta_host;
   bool dense_mix = false;          // some sweep program failed its check: dense matrices
+  size_t hop_min_lds = 0;          // lower bound on a fused hop block's LDS (limits occupancy)
   std::vector<double> h_mix;
   // links per precision
   dwa::PrecFields prec[3];

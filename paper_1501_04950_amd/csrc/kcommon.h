@@ -988,7 +988,8 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
     return DWA_EINVAL;
   }
   const unsigned grid = (unsigned)((ctx->Vh + NS - 1) / NS);
-  const size_t shm = hop_mix_lds_bytes<RealOf<S>>(NS, Ls);
+  size_t shm = hop_mix_lds_bytes<RealOf<S>>(NS, Ls);
+  if (shm < ctx->hop_min_lds) shm = ctx->hop_min_lds;
   const dim3 block(NS * Ls);
   const int mode = op.pre ? 2 : (op.post ? 1 : 0);
   if (op.pre && op.post) {
