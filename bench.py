@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the alpha sweep")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 512 MiB device copy (scale reference for HBM counters)")
@@ -174,6 +175,42 @@ def main():
     if y64 is not None:
         y_err = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
 
+    # --- alpha study (Sec. 3): FP64 CGNE iteration counts n(alpha) -------------------
+    sweep = None
+    if not args.no_sweep:
+        alphas = [round(0.5 + 0.1 * i, 2) for i in range(11)]
+        log(f"alpha sweep {alphas[0]}..{alphas[-1]} (FP64)")
+        ys, sts, rc = ctx.alpha_sweep(eta_d, alphas, tol=args.tol, inner_prec="f64",
+                                      check_every=1)
+        iters = [st["iters"] for st in sts]
+        n1 = iters[alphas.index(1.0)]
+        best = min(range(len(alphas)), key=lambda i: iters[i])
+        ratio = iters[best] / n1
+        y_ref = ys[alphas.index(1.0)]
+        spread = max(float(torch.linalg.vector_norm(ys[i] - y_ref) / torch.linalg.vector_norm(y_ref))
+                     for i in range(len(alphas)))
+        sweep = {"alpha": alphas, "iters": iters, "rel_iters": [round(i / n1, 4) for i in iters],
+                 "time_s": [round(st["time_ms"] / 1e3, 4) for st in sts],
+                 "best_alpha": alphas[best], "best_rel_iters": round(ratio, 4),
+                 "speedup_1_minus_ratio": round(1 - ratio, 4),
+                 "speedup_inverse_ratio_minus_1": round(1 / ratio - 1, 4),
+                 "y1_max_rel_diff_across_alpha": spread}
+        log(f"  iters {iters}; best alpha {alphas[best]} ratio {ratio:.3f}; y1 spread {spread:.1e}")
+        del ys
+        # the mixed-precision solve again at the best alpha (same y_1, fewer iterations)
+        ctx.set_alpha(alphas[best])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        yb, stb, rcb = ctx.propagator(eta_d, **kw)
+        torch.cuda.synchronize()
+        sweep["mixed_at_best_alpha"] = {
+            "alpha": alphas[best], "time_s": round(time.perf_counter() - t0, 4),
+            "iters": stb["iters"], "rel_resid": stb["rel_resid"],
+            "y1_rel_diff_vs_alpha1": float(torch.linalg.vector_norm(yb - y) / torch.linalg.vector_norm(y))}
+        ctx.set_alpha(args.alpha)
+        log(f"  mixed at alpha {alphas[best]}: {sweep['mixed_at_best_alpha']['time_s']} s, "
+            f"{stb['iters']} iters")
+
     # --- CPU oracle on a bounded sample ---------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -215,6 +252,7 @@ def main():
         "speedup_mixed_vs_fp64": round(fp64["time_s"] / mixed_s, 3) if fp64 else None,
         "dbb": {p: {k: round(v, 2) for k, v in kern[p].items()} for p in kern},
         "roofline": roofline,
+        "alpha_sweep": sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)

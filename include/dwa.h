@@ -178,6 +178,22 @@ int dwa_cgne_solve(dwa_ctx *ctx, void *x_b, const void *rhs_b, const dwa_solve_o
 int dwa_propagator(dwa_ctx *ctx, void *y1, const void *eta, const dwa_solve_opts *opts,
                    dwa_solve_stats *stats, void *psi5);
 
+/* Change alpha of an existing context (eq.(mobius1): alpha multiplies the P+/P- terms
+ * of every row; the 4D propagator does not depend on it, Sec. 2 / eq.(tosolve1)).
+ * Rebuilds the site-local matrices for the new alpha after the context's stream has
+ * drained; links and workspace are kept.  DWA_EINVAL for alpha = 0, non-finite alpha
+ * or a singular I, with the context unchanged. */
+int dwa_set_alpha(dwa_ctx *ctx, double alpha);
+
+/* The alpha study of Sec. 3: for each alphas[i] (i < n) solve for y_1 of eta with the
+ * options opts and record the solve statistics in stats[i] (iteration counts n(alpha)
+ * under the residual of eq.(redblack)).  y1 receives n canonical complex128 [V][4][3]
+ * fields back to back (device, n * V * 12 * 16 bytes).  The context's alpha is
+ * restored on return.  Returns the first status other than DWA_OK (DWA_ENOCONV of a
+ * single alpha does not stop the sweep). */
+int dwa_alpha_sweep(dwa_ctx *ctx, const double *alphas, int n, void *y1, const void *eta,
+                    const dwa_solve_opts *opts, dwa_solve_stats *stats);
+
 const char *dwa_strerror(int status);
 const char *dwa_last_error(void);
 

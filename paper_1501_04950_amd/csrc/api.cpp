@@ -444,6 +444,34 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   return status;
 }
 
+// Upload the site-local matrices and sweep tables of the context's parameters
+// (allocating the device tables on first use; their sizes depend on Ls only).
+int upload_smatrices(dwa_ctx* ctx, const std::vector<double>& mix, const SweepTables& sweeps,
+                     bool alloc) {
+  std::vector<float> mix32(mix.begin(), mix.end());
+  std::vector<float> sw32(sweeps.coef.begin(), sweeps.coef.end());
+  if (alloc) {
+    DWA_HIP(hipMalloc(&ctx->d_mix64, sizeof(double) * mix.size()), "alloc mix");
+    DWA_HIP(hipMalloc(&ctx->d_mix32, sizeof(float) * mix.size()), "alloc mix32");
+    DWA_HIP(hipMalloc(&ctx->d_sweep_meta, sizeof(int) * sweeps.meta.size()), "alloc sweep meta");
+    DWA_HIP(hipMalloc(&ctx->d_sweep64, sizeof(double) * sweeps.coef.size()), "alloc sweep64");
+    DWA_HIP(hipMalloc(&ctx->d_sweep32, sizeof(float) * sw32.size()), "alloc sweep32");
+  }
+  DWA_HIP(hipMemcpy(ctx->d_mix64, mix.data(), sizeof(double) * mix.size(), hipMemcpyHostToDevice), "upload mix");
+  DWA_HIP(hipMemcpy(ctx->d_mix32, mix32.data(), sizeof(float) * mix32.size(), hipMemcpyHostToDevice), "upload mix32");
+  DWA_HIP(hipMemcpy(ctx->d_sweep_meta, sweeps.meta.data(), sizeof(int) * sweeps.meta.size(), hipMemcpyHostToDevice),
+          "upload sweep meta");
+  DWA_HIP(hipMemcpy(ctx->d_sweep64, sweeps.coef.data(), sizeof(double) * sweeps.coef.size(), hipMemcpyHostToDevice),
+          "upload sweep64");
+  DWA_HIP(hipMemcpy(ctx->d_sweep32, sw32.data(), sizeof(float) * sw32.size(), hipMemcpyHostToDevice), "upload sweep32");
+  ctx->h_mix = mix;
+  ctx->sweep_meta_host = sweeps.meta;
+  ctx->dense_mix = std::getenv("DWA_DENSE_MIX") != nullptr;
+  for (size_t k = 0; k < sweeps.meta.size(); k += 4)
+    if (sweeps.meta[k + 1] == ST_DENSE) ctx->dense_mix = true;
+  return DWA_OK;
+}
+
 int check_ctx(dwa_ctx* ctx) {
   if (!ctx) return einval("null context");
   if (!ctx->links_set) {
@@ -596,34 +624,9 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
       return fail(rc);
   }
   // s-matrices
-  std::vector<float> mix32(mix.begin(), mix.end());
-  if ((rc = hip_fail(hipMalloc(&ctx->d_mix64, sizeof(double) * mix.size()), "alloc mix"))) return fail(rc);
-  if ((rc = hip_fail(hipMalloc(&ctx->d_mix32, sizeof(float) * mix.size()), "alloc mix32"))) return fail(rc);
-  if ((rc = hip_fail(hipMemcpy(ctx->d_mix64, mix.data(), sizeof(double) * mix.size(), hipMemcpyHostToDevice), "upload mix")))
-    return fail(rc);
-  if ((rc = hip_fail(hipMemcpy(ctx->d_mix32, mix32.data(), sizeof(float) * mix32.size(), hipMemcpyHostToDevice), "upload mix32")))
-    return fail(rc);
-  {
-    std::vector<float> sw32(sweeps.coef.begin(), sweeps.coef.end());
-    if ((rc = hip_fail(hipMalloc(&ctx->d_sweep_meta, sizeof(int) * sweeps.meta.size()), "alloc sweep meta")))
-      return fail(rc);
-    if ((rc = hip_fail(hipMalloc(&ctx->d_sweep64, sizeof(double) * sweeps.coef.size()), "alloc sweep64")))
-      return fail(rc);
-    if ((rc = hip_fail(hipMalloc(&ctx->d_sweep32, sizeof(float) * sw32.size()), "alloc sweep32")))
-      return fail(rc);
-    if ((rc = hip_fail(hipMemcpy(ctx->d_sweep_meta, sweeps.meta.data(), sizeof(int) * sweeps.meta.size(), hipMemcpyHostToDevice), "upload sweep meta")))
-      return fail(rc);
-    if ((rc = hip_fail(hipMemcpy(ctx->d_sweep64, sweeps.coef.data(), sizeof(double) * sweeps.coef.size(), hipMemcpyHostToDevice), "upload sweep64")))
-      return fail(rc);
-    if ((rc = hip_fail(hipMemcpy(ctx->d_sweep32, sw32.data(), sizeof(float) * sw32.size(), hipMemcpyHostToDevice), "upload sweep32")))
-      return fail(rc);
-    ctx->sweep_meta_host = sweeps.meta;
-    for (size_t k = 0; k < sweeps.meta.size(); k += 4)
-      if (sweeps.meta[k + 1] == ST_DENSE) ctx->dense_mix = true;
-    if (std::getenv("DWA_DENSE_MIX")) ctx->dense_mix = true;
-    if (const char* e = std::getenv("DWA_HOP_MIN_LDS_KB"))
-      ctx->hop_min_lds = std::min<size_t>(size_t(std::max(0, std::atoi(e))) * 1024, 160 * 1024);
-  }
+  if ((rc = upload_smatrices(ctx, mix, sweeps, true))) return fail(rc);
+  if (const char* e = std::getenv("DWA_HOP_MIN_LDS_KB"))
+    ctx->hop_min_lds = std::min<size_t>(size_t(std::max(0, std::atoi(e))) * 1024, 160 * 1024);
   // links and workspace
   const size_t n = field_elems(ctx);
   for (int pr = 0; pr < 3; ++pr)
@@ -669,6 +672,21 @@ int dwa_destroy(dwa_ctx* ctx) {
   f(ctx->d_red);
   if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
   delete ctx;
+  return DWA_OK;
+}
+
+int dwa_set_alpha(dwa_ctx* ctx, double alpha) {
+  if (!ctx) return einval("null context");
+  if (!std::isfinite(alpha) || alpha == 0.0) return einval("alpha must be finite and non-zero");
+  std::vector<double> mix;
+  std::string err;
+  SweepTables sweeps;
+  if (!build_smatrices(ctx->Ls, ctx->M5, ctx->m, alpha, ctx->b.data(), ctx->c.data(), mix, err, &sweeps))
+    return einval(err);
+  // work already queued may read the current tables
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "set_alpha sync");
+  DWA_TRY(upload_smatrices(ctx, mix, sweeps, false));
+  ctx->alpha = alpha;
   return DWA_OK;
 }
 
@@ -847,6 +865,30 @@ int dwa_propagator(dwa_ctx* ctx, void* y1, const void* eta, const dwa_solve_opts
   }
   DWA_HIP(hipStreamSynchronize(ctx->stream), "propagator sync");
   return status;
+}
+
+int dwa_alpha_sweep(dwa_ctx* ctx, const double* alphas, int n, void* y1, const void* eta,
+                    const dwa_solve_opts* o, dwa_solve_stats* stats) {
+  DWA_TRY(check_ctx(ctx));
+  if (!alphas || n < 1 || !y1 || !eta || !o || !stats) return einval("null argument or n < 1");
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(alphas[i]) || alphas[i] == 0.0) return einval("alpha must be finite and non-zero");
+  const double alpha0 = ctx->alpha;
+  const size_t field_bytes = size_t(ctx->V) * 12 * 16;
+  int first = DWA_OK;
+  for (int i = 0; i < n; ++i) {
+    int rc = dwa_set_alpha(ctx, alphas[i]);
+    if (rc == DWA_OK)
+      rc = dwa_propagator(ctx, static_cast<char*>(y1) + i * field_bytes, eta, o, &stats[i], nullptr);
+    if (rc != DWA_OK && rc != DWA_ENOCONV) {
+      (void)dwa_set_alpha(ctx, alpha0);
+      return rc;
+    }
+    if (rc != DWA_OK && first == DWA_OK) first = rc;
+  }
+  DWA_TRY(dwa_set_alpha(ctx, alpha0));
+  if (first == DWA_ENOCONV) set_error("solver reached maxiter or stagnated for some alpha");
+  return first;
 }
 
 // Host-only access to the site-local matrices (no device needed); used to check

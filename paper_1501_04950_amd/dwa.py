@@ -88,6 +88,9 @@ def lib():
         "dwa_apply_hop": (c_int, [P, c_int, c_int, c_int, P, P]),
         "dwa_cgne_solve": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats)]),
         "dwa_propagator": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats), P]),
+        "dwa_set_alpha": (c_int, [P, c_double]),
+        "dwa_alpha_sweep": (c_int, [P, POINTER(c_double), c_int, P, P, POINTER(dwa_solve_opts),
+                                    POINTER(dwa_solve_stats)]),
         "dwa_strerror": (ctypes.c_char_p, [c_int]),
         "dwa_last_error": (ctypes.c_char_p, []),
         "dwa_debug_smatrix": (c_int, [POINTER(dwa_params), c_int, POINTER(c_double)]),
@@ -292,3 +295,21 @@ class Context:
         if want_psi:
             return y1, st.as_dict(), rc, psi
         return y1, st.as_dict(), rc
+
+    def set_alpha(self, alpha):
+        check(lib().dwa_set_alpha(self._h, float(alpha)))
+        self.params.alpha = float(alpha)
+
+    def alpha_sweep(self, eta, alphas, **kw):
+        """The alpha study: y_1 and solve statistics for each alpha (Sec. 3).
+        Returns (y1 [n, V, 4, 3], list of stats dicts, status)."""
+        torch = _torch()
+        self._check_canon(eta, (self.V, 4, 3))
+        a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).ravel())
+        n = a.size
+        y1 = torch.zeros((n, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        o = self.opts(**kw)
+        st = (dwa_solve_stats * n)()
+        rc = check(lib().dwa_alpha_sweep(self._h, a.ctypes.data_as(POINTER(c_double)), n, _ptr(y1),
+                                         _ptr(eta), byref(o), st), allow=(DWA_ENOCONV,))
+        return y1, [st[i].as_dict() for i in range(n)], rc

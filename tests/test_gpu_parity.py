@@ -223,6 +223,76 @@ def test_y1_alpha_independent_on_gpu():
     assert rel(ys[0], ys[1]) < 1e-9 and rel(ys[2], ys[1]) < 1e-9
 
 
+def test_alpha_sweep_matches_oracle():
+    """The alpha study on one context (dwa_set_alpha between solves): each alpha's
+    iteration count is the oracle CGLS count at that alpha (within one), every y_1
+    is the oracle's alpha = 1 propagator, and the context's alpha is restored."""
+    cs = case("c1_4x4x4x4_ls8")
+    eta = synth.point_source(cs.dims, 0, 1, 0)
+    alphas = [0.5, 0.8, 1.0, 1.2]
+    ref_iters = []
+    y_ref = None
+    for a in alphas:
+        y_a, info = redblack.propagator(cs.U, eta, cs.p.with_(alpha=a), tol=1e-10)
+        ref_iters.append(info.iters)
+        if a == 1.0:
+            y_ref = y_a
+    ctx = cs.ctx()
+    say(f"[gpu] alpha sweep c1 {alphas}")
+    y, stats, rc = ctx.alpha_sweep(torch.from_numpy(eta).to(gpu()), alphas, tol=1e-10, check_every=1)
+    assert rc == dwa.DWA_OK
+    iters = [st["iters"] for st in stats]
+    say(f"    iters gpu {iters} oracle {ref_iters}")
+    for a, i, r, st, yy in zip(alphas, iters, ref_iters, stats, y.cpu().numpy()):
+        assert abs(i - r) <= 1, (a, i, r)
+        assert st["rel_resid"] <= 1.5e-10
+        assert rel(yy, y_ref) < 1e-8
+    # restored: a plain solve reproduces the context's own alpha count
+    _, st0, _ = ctx.propagator(torch.from_numpy(eta).to(gpu()), tol=1e-10, check_every=1)
+    assert abs(st0["iters"] - ref_iters[alphas.index(cs.alpha)]) <= 1
+    with pytest.raises(dwa.DwaError) as e:
+        ctx.set_alpha(0.0)
+    assert e.value.status == dwa.DWA_EINVAL
+    ctx.close()
+
+
+def test_alpha_sweep_8x8x8x16_fp64_and_f32():
+    """The alpha study on 8^3 x 16, Ls = 12 (spread 0.5, m = 0.02) for the 12 spin-colour
+    point sources at site 0, FP64 and FP32-inner with FP64 reliable updates, both to a
+    1e-10 residual.  Properties that hold at any size: every solve converges, y_1 is the
+    same for every alpha and both precisions (within kappa * tol), and the FP32 path
+    needs about as many iterations as FP64.  The iteration counts are printed (the
+    paper's MILC fields are not here, so their values are not pinned)."""
+    name = "c2_8x8x8x16_ls12"
+    w = synth.WORKLOADS[name]
+    dev = gpu()
+    ctx = dwa.Context(w["dims"], w["Ls"], w["M5"], w["m"], 1.0, w["b"], w["c"])
+    ctx.set_links(torch.from_numpy(synth.workload_links(name)).to(dev))
+    alphas = list(w["alphas"])
+    n = {"f64": np.zeros((12, len(alphas)), int), "f32": np.zeros((12, len(alphas)), int)}
+    for src in range(12):
+        eta = torch.from_numpy(synth.point_source(w["dims"], 0, src // 3, src % 3)).to(dev)
+        say(f"[gpu] c2 alpha sweep source {src}")
+        y64, st64, rc64 = ctx.alpha_sweep(eta, alphas, tol=1e-10, check_every=10)
+        y32, st32, rc32 = ctx.alpha_sweep(eta, alphas, tol=1e-10, inner_prec="f32", delta=0.05,
+                                          check_every=10)
+        assert rc64 == dwa.DWA_OK and rc32 == dwa.DWA_OK
+        ref = y64[alphas.index(1.0)]
+        for k in range(len(alphas)):
+            assert st64[k]["rel_resid"] <= 1e-10 and st32[k]["rel_resid"] <= 1e-10
+            for y in (y64[k], y32[k]):
+                d = float(torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref))
+                assert d < 1e-7, (src, alphas[k], d)
+            n["f64"][src, k] = st64[k]["iters"]
+            n["f32"][src, k] = st32[k]["iters"]
+    for prec in ("f64", "f32"):
+        rel_n = n[prec] / n[prec][:, [alphas.index(1.0)]]
+        say(f"    {prec}: mean n(alpha)/n(1) " +
+            ", ".join(f"{a}: {m:.3f}+-{sd:.3f}" for a, m, sd in zip(alphas, rel_n.mean(0), rel_n.std(0))))
+    assert np.all(n["f32"] <= 1.3 * n["f64"] + 20)
+    ctx.close()
+
+
 @pytest.mark.parametrize("inner", ["f32", "bf16"])
 def test_mixed_precision_reaches_fp64_accuracy(inner):
     cs = case("c1_4x4x4x4_ls8")
