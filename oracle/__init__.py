@@ -18,6 +18,9 @@ better conditioned Domain Wall Operator"):
 * ``redblack`` -- the red-black form D_bb = 1 - I_bb^-1 D_br I_rr^-1 D_rb of
                   eq.(redblack), its adjoint, CG on the normal equations, and
                   the propagator y_1 of eq.(tosolve)/(tosolve1).
+* ``adjoint``  -- gradients of L = Re <eta', y_1> with respect to the links,
+                  the source, alpha, b_i and c_i by the adjoint-state method,
+                  term by term from the block matrix of eq.(mobius1).
 * ``overlap``  -- dense and closed-form tools used only as pins: the dense
                   transfer-matrix overlap operator of Appendix A and the free
                   field momentum-space operator.
