@@ -194,6 +194,26 @@ int dwa_set_alpha(dwa_ctx *ctx, double alpha);
 int dwa_alpha_sweep(dwa_ctx *ctx, const double *alphas, int n, void *y1, const void *eta,
                     const dwa_solve_opts *opts, dwa_solve_stats *stats);
 
+/* Gradients of L = Re <eta', y_1> by the adjoint-state method (no equation of the paper
+ * defines them; they follow from eq.(tosolve) / eq.(tosolve1) with y_1 = E psi,
+ * D_alpha(m) psi = D_1(1) P b).  One forward solve gives psi, one adjoint solve gives
+ * lambda with D_alpha(m)^dag lambda = E^dag eta' (red-black: CGNE on D_bb^dag, FP64),
+ * and dL = Re <lambda, d(D_1(1) P b) - (d D_alpha) psi> is evaluated for
+ *   gU     device complex128 [4][V][3][3]: dL/dRe U + i dL/dIm U per link entry, the
+ *          link perturbation entering the backward hop as its conjugate transpose,
+ *   geta   device complex128 [V][4][3]: dL/dRe eta + i dL/dIm eta,
+ *   galpha host double: dL/dalpha (zero up to rounding: y_1 does not depend on alpha),
+ *   gb, gc host double [Ls]: dL/db_s, dL/dc_s,
+ *   L      host double: the loss, y1 device [V][4][3]: the propagator.
+ * Any output may be NULL.  eta and eta_prime are device complex128 [V][4][3].  opts
+ * applies to the forward solve (any inner precision) and, as FP64 CGNE, to the
+ * adjoint solve; stats (may be NULL) receives two entries: forward, adjoint.
+ * Returns DWA_ENOCONV if either solve did not converge (outputs still written). */
+int dwa_propagator_adjoint(dwa_ctx *ctx, void *gU, void *geta, double *galpha, double *gb,
+                           double *gc, double *L, void *y1, const void *eta,
+                           const void *eta_prime, const dwa_solve_opts *opts,
+                           dwa_solve_stats *stats);
+
 const char *dwa_strerror(int status);
 const char *dwa_last_error(void);
 

@@ -15,7 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SOURCES = ["csrc/kernels_f64.hip", "csrc/kernels_f32.hip", "csrc/kernels_bf16.hip",
-           "csrc/kernels.hip", "csrc/api.cpp", "csrc/smat.cpp"]
+           "csrc/kernels.hip", "csrc/adjoint.hip", "csrc/api.cpp", "csrc/smat.cpp"]
 LIB = os.path.join(PKG, "libdwa.so")
 OBJDIR = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

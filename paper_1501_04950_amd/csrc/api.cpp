@@ -132,7 +132,7 @@ struct CgResult {
 };
 
 int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol, int maxiter,
-         int check_every, CgResult* res) {
+         int check_every, CgResult* res, bool adj = false) {
   void** W = low_pool(ctx, prec);
   const bool p64 = prec == DWA_F64;
   void* r = W[p64 ? W_R : L_R];
@@ -151,8 +151,21 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
     set_error("warm-started CGLS needs FP64 storage");
     return DWA_EINVAL;
   }
+  // A is D_bb, or D_bb^dag for adj (CGLS on the adjoint system); the premixed input of
+  // A (u, from p) and of A^dag (w, from r) follow
+  const int mixA = adj ? MIX_G5_IINVT_GINV : MIX_BG;
+  const int mixAd = adj ? MIX_BG : MIX_G5_IINVT_GINV;
+  auto applyA = [&](void* out, const void* in, const void* pre, double* part, int* nb) {
+    return adj ? dbbdag_from_premix(ctx, prec, out, in, pre, t, part, nb)
+               : dbb_from_premix(ctx, prec, out, in, pre, t, part, nb);
+  };
+  auto applyAd = [&](void* out, const void* in, const void* pre, double* part, int* nb) {
+    return adj ? dbb_from_premix(ctx, prec, out, in, pre, t, part, nb)
+               : dbbdag_from_premix(ctx, prec, out, in, pre, t, part, nb);
+  };
   if (warm) {
-    DWA_TRY(apply_dbb(ctx, prec, q, x, u, t));
+    DWA_TRY(launch_smix(ctx, prec, mixA, u, x, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+    DWA_TRY(applyA(q, x, u, nullptr, nullptr));
     DWA_TRY(launch_axpby(ctx, prec, r, 1.0, rhs, 0.0, n));
     DWA_TRY(launch_axpby(ctx, prec, r, -1.0, q, 1.0, n));
     res->n_dbb += 1;
@@ -160,9 +173,9 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
     DWA_TRY(launch_zero(ctx, xacc_prec(prec), x, n));
     DWA_TRY(launch_axpby(ctx, prec, r, 1.0, rhs, 0.0, n));
   }
-  // z = D_bb^dag r, gamma = |z|^2, |rhs|^2
-  DWA_TRY(launch_smix(ctx, prec, MIX_G5_IINVT_GINV, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
-  DWA_TRY(dbbdag_from_premix(ctx, prec, z, r, w, t, bank(ctx, 0), &nbA));
+  // z = A^dag r, gamma = |z|^2, |rhs|^2
+  DWA_TRY(launch_smix(ctx, prec, mixAd, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
   DWA_TRY(launch_norm2(ctx, prec, rhs, n, bank(ctx, 1), &nbB));
   DWA_TRY(launch_cg_finalize(ctx, 2, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
   if (warm) {
@@ -171,7 +184,7 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
   }
   res->n_dbb += 1;
   DWA_TRY(launch_axpby(ctx, prec, p, 1.0, z, 0.0, n));
-  DWA_TRY(launch_smix(ctx, prec, MIX_BG, u, p, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  DWA_TRY(launch_smix(ctx, prec, mixA, u, p, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
 
   const double tol2 = tol * tol;
   int k = 0;
@@ -190,16 +203,16 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
       }
       if (k >= maxiter) break;
     }
-    // q = D_bb p (premixed u = B G p), |q|^2, a = gamma / |q|^2
-    DWA_TRY(dbb_from_premix(ctx, prec, q, p, u, t, bank(ctx, 0), &nbA));
+    // q = A p (premixed u), |q|^2, a = gamma / |q|^2
+    DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
     DWA_TRY(launch_cg_finalize(ctx, 0, sc, bank(ctx, 0), nbA, nullptr, 0));
-    // x += a p ; r -= a q ; |r|^2 ; w = g5 I^-T G^-1 r
-    DWA_TRY(launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB));
-    // z = D_bb^dag r, beta = |z|^2 / gamma
-    DWA_TRY(dbbdag_from_premix(ctx, prec, z, r, w, t, bank(ctx, 0), &nbA));
+    // x += a p ; r -= a q ; |r|^2 ; w = premix of r for A^dag
+    DWA_TRY(launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB, adj));
+    // z = A^dag r, beta = |z|^2 / gamma
+    DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
     DWA_TRY(launch_cg_finalize(ctx, 1, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
-    // p = z + beta p ; u = B G p
-    DWA_TRY(launch_cg_update2(ctx, prec, p, u, z, sc));
+    // p = z + beta p ; u = premix of p for A
+    DWA_TRY(launch_cg_update2(ctx, prec, p, u, z, sc, adj));
     res->n_dbb += 2;
     ++k;
   }
@@ -889,6 +902,173 @@ int dwa_alpha_sweep(dwa_ctx* ctx, const double* alphas, int n, void* y1, const v
   DWA_TRY(dwa_set_alpha(ctx, alpha0));
   if (first == DWA_ENOCONV) set_error("solver reached maxiter or stagnated for some alpha");
   return first;
+}
+
+// Per-slice Re <a, b> over both parities (a times g5 when g5), summed on the host in
+// a fixed order.  a[2] / b[2]: black and red SoA fields of nslices slices.
+static int host_slice_dots(dwa_ctx* ctx, const void* const a[2], const void* const b[2], int nslices,
+                    bool g5, double* out) {
+  const int nb = slice_dot_blocks(12 * size_t(ctx->Vh));
+  std::vector<double> h(size_t(nslices) * nb);
+  for (int s = 0; s < nslices; ++s) out[s] = 0.0;
+  for (int par = 0; par < 2; ++par) {
+    DWA_TRY(launch_slice_dot(ctx, a[par], b[par], nslices, ctx->Vh, g5, bank(ctx, 2)));
+    DWA_HIP(hipMemcpyAsync(h.data(), bank(ctx, 2), sizeof(double) * h.size(), hipMemcpyDeviceToHost,
+                           ctx->stream), "dot readback");
+    DWA_HIP(hipStreamSynchronize(ctx->stream), "dot sync");
+    for (int s = 0; s < nslices; ++s)
+      for (int k = 0; k < nb; ++k) out[s] += h[size_t(s) * nb + k];
+  }
+  return DWA_OK;
+}
+
+int dwa_propagator_adjoint(dwa_ctx* ctx, void* gU, void* geta, double* galpha, double* gb,
+                           double* gc, double* L, void* y1, const void* eta, const void* eta_p,
+                           const dwa_solve_opts* o, dwa_solve_stats* stats) {
+  DWA_TRY(check_ctx(ctx));
+  if (!eta || !eta_p || !o) return einval("null argument");
+  const int Ls = ctx->Ls;
+  const size_t Vh = size_t(ctx->Vh);
+  const size_t n = field_elems(ctx);
+  const size_t slice = 12 * Vh;  // complex numbers per half-field slice
+  void** W = ctx->w64;
+  dwa_solve_stats st[2]{};
+
+  // forward: psi (W_PSI_B/R), chi' = B_1 P b (W_CHI_B/R), y_1
+  void* ybuf = y1 ? y1 : W[W_X];
+  int status = dwa_propagator(ctx, ybuf, eta, o, &st[0], nullptr);
+  if (status != DWA_OK && status != DWA_ENOCONV) return status;
+  if (L) {
+    const void* a[2] = {eta_p, nullptr};
+    const void* b[2] = {ybuf, nullptr};
+    const int nb = slice_dot_blocks(12 * 2 * Vh);
+    std::vector<double> h(nb);
+    DWA_TRY(launch_slice_dot(ctx, a[0], b[0], 1, 2 * Vh, false, bank(ctx, 2)));
+    DWA_HIP(hipMemcpyAsync(h.data(), bank(ctx, 2), sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream),
+            "loss readback");
+    DWA_HIP(hipStreamSynchronize(ctx->stream), "loss sync");
+    double v = 0.0;
+    for (int k = 0; k < nb; ++k) v += h[k];
+    *L = v;
+  }
+
+  // adjoint: D_alpha^dag lambda = f = E^dag eta' through the red-black Schur form,
+  //   g_b = f_b - D_rb^dag I^-dag f_r = f_b + 1/2 G B^T g5 H_br (g5 I_1^-T G^-1 f_r),
+  //   D_bb^dag mu_b = g_b (CGLS on D_bb^dag),  g5 lambda_b = g5 I_1^-T G^-1 mu_b,
+  //   g5 lambda_r = g5 I_1^-T G^-1 (f_r + 1/2 G B^T g5 H_rb (g5 lambda_b)).
+  void* f_b = W[W_RHO_B];
+  void* f_r = W[W_RHO_R];
+  DWA_TRY(launch_adj_source(ctx, f_b, f_r, eta_p));
+  DWA_TRY(launch_smix(ctx, DWA_F64, MIX_G5_IINVT_GINV, W[W_OPR], f_r, nullptr, 0.0, Ls, nullptr, nullptr));
+  HopOp hg{W[W_OPR], W[W_PHI], nullptr, f_b, 0.5, 0.0, 1.0, MIX_G_BT_G5, 0, Ls, nullptr};
+  DWA_TRY(launch_hop(ctx, DWA_F64, hg, nullptr));
+  {
+    const auto t0 = std::chrono::steady_clock::now();
+    CgResult cr;
+    DWA_TRY(cgls(ctx, DWA_F64, W[W_X], W[W_PHI], false, o->tol, o->maxiter, o->check_every, &cr, true));
+    double g2 = 0.0;
+    DWA_TRY(host_norm2(ctx, DWA_F64, W[W_PHI], &g2));
+    DWA_TRY(apply_dbbdag(ctx, DWA_F64, W[W_Q], W[W_X], W[W_OPB], W[W_OPR]));
+    DWA_TRY(launch_axpby(ctx, DWA_F64, W[W_RES], 1.0, W[W_PHI], 0.0, n));
+    DWA_TRY(launch_axpby(ctx, DWA_F64, W[W_RES], -1.0, W[W_Q], 1.0, n));
+    double r2 = 0.0;
+    DWA_TRY(host_norm2(ctx, DWA_F64, W[W_RES], &r2));
+    st[1].iters = cr.iters;
+    st[1].converged = cr.converged;
+    st[1].rel_resid = g2 > 0 ? std::sqrt(r2 / g2) : 0.0;
+    st[1].n_Dbb = cr.n_dbb + 1;
+    st[1].time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (cr.breakdown) {
+      set_error("CG breakdown in the adjoint solve");
+      return DWA_EBREAKDOWN;
+    }
+    if (!cr.converged && status == DWA_OK) status = DWA_ENOCONV;
+  }
+  void* lt_b = W[W_P];
+  void* lt_r = W[W_Z];
+  DWA_TRY(launch_smix(ctx, DWA_F64, MIX_G5_IINVT_GINV, lt_b, W[W_X], nullptr, 0.0, Ls, nullptr, nullptr));
+  HopOp hl{lt_b, W[W_Q], nullptr, f_r, 0.5, 0.0, 1.0, MIX_G_BT_G5, 1, Ls, nullptr};
+  DWA_TRY(launch_hop(ctx, DWA_F64, hl, nullptr));
+  DWA_TRY(launch_smix(ctx, DWA_F64, MIX_G5_IINVT_GINV, lt_r, W[W_Q], nullptr, 0.0, Ls, nullptr, nullptr));
+  const void* lt[2] = {lt_b, lt_r};
+
+  // links: phi = B_1 P b - B G psi on both parities, then the force kernel
+  if (gU) {
+    void* ph_b = W[W_R];
+    void* ph_r = W[W_T];
+    DWA_TRY(launch_smix(ctx, DWA_F64, MIX_BG, ph_b, W[W_PSI_B], nullptr, 0.0, Ls, nullptr, nullptr));
+    DWA_TRY(launch_smix(ctx, DWA_F64, MIX_BG, ph_r, W[W_PSI_R], nullptr, 0.0, Ls, nullptr, nullptr));
+    DWA_TRY(launch_axpby(ctx, DWA_F64, ph_b, 1.0, W[W_CHI_B], -1.0, n));
+    DWA_TRY(launch_axpby(ctx, DWA_F64, ph_r, 1.0, W[W_CHI_R], -1.0, n));
+    DWA_TRY(launch_force(ctx, gU, lt_b, lt_r, ph_b, ph_r));
+  }
+
+  // b_s, c_s: Re <lambda_s, (D_w omega)_s> with D_w omega = (4 + M5) omega - 1/2 H omega
+  auto dw_full = [&](void* out_b, void* out_r, const void* in_b, const void* in_r) {
+    HopOp ob{in_r, out_b, in_b, nullptr, -0.5, 4.0 + ctx->M5, 0.0, MIX_IDENTITY, 0, Ls, nullptr};
+    HopOp orr{in_b, out_r, in_r, nullptr, -0.5, 4.0 + ctx->M5, 0.0, MIX_IDENTITY, 1, Ls, nullptr};
+    int rc = launch_hop(ctx, DWA_F64, ob, nullptr);
+    return rc == DWA_OK ? launch_hop(ctx, DWA_F64, orr, nullptr) : rc;
+  };
+  if (gb || gc) {
+    DWA_TRY(launch_omega(ctx, W[W_W], W[W_U], W[W_PSI_B], eta, 0));
+    DWA_TRY(launch_omega(ctx, W[W_OPB], W[W_OPR], W[W_PSI_R], eta, 1));
+    const void* dws[2] = {W[W_RES], W[W_PHI]};
+    if (gb) {
+      DWA_TRY(dw_full(W[W_RES], W[W_PHI], W[W_W], W[W_OPB]));
+      DWA_TRY(host_slice_dots(ctx, lt, dws, Ls, true, gb));
+    }
+    if (gc) {
+      DWA_TRY(dw_full(W[W_RES], W[W_PHI], W[W_U], W[W_OPR]));
+      DWA_TRY(host_slice_dots(ctx, lt, dws, Ls, true, gc));
+    }
+  }
+
+  // alpha: d D_alpha / d alpha = D_1 dG/dalpha = D_alpha (J / alpha), J = diag(P+, 1, .., 1, P-),
+  // so dL/dalpha = -Re <lambda, D_alpha J psi> / alpha, with D_alpha = I_1 G - 1/2 H B G
+  if (galpha) {
+    void* v[2] = {W[W_W], W[W_U]};
+    void* out[2] = {W[W_OPB], W[W_PHI]};
+    DWA_TRY(launch_jpsi(ctx, v[0], W[W_PSI_B]));
+    DWA_TRY(launch_jpsi(ctx, v[1], W[W_PSI_R]));
+    for (int par = 0; par < 2; ++par) {
+      DWA_TRY(launch_smix(ctx, DWA_F64, MIX_BG, W[W_OPR], v[1 - par], nullptr, 0.0, Ls, nullptr, nullptr));
+      HopOp hh{W[W_OPR], W[W_RES], nullptr, nullptr, -0.5, 0.0, 0.0, MIX_IDENTITY, par, Ls, nullptr};
+      DWA_TRY(launch_hop(ctx, DWA_F64, hh, nullptr));
+      DWA_TRY(launch_smix(ctx, DWA_F64, MIX_I_ALPHA, out[par], v[par], W[W_RES], 1.0, Ls, nullptr, nullptr));
+    }
+    std::vector<double> d(Ls);
+    const void* outc[2] = {out[0], out[1]};
+    DWA_TRY(host_slice_dots(ctx, lt, outc, Ls, true, d.data()));
+    double sum = 0.0;
+    for (int s2 = 0; s2 < Ls; ++s2) sum += d[s2];
+    *galpha = -sum / ctx->alpha;
+  }
+
+  // eta: u = D_w^dag lambda = g5 D_w (g5 lambda) on the wall slices, then combine
+  if (geta) {
+    const size_t last = size_t(Ls - 1);
+    for (int par = 0; par < 2; ++par) {
+      void* dst = par ? W[W_PHI] : W[W_RES];
+      const void* own = lt[par];
+      const void* other = lt[1 - par];
+      for (int k = 0; k < 2; ++k) {
+        const size_t sidx = k ? last : 0;
+        HopOp h{static_cast<const double2*>(other) + sidx * slice, static_cast<double2*>(dst) + k * slice,
+                static_cast<const double2*>(own) + sidx * slice, nullptr, -0.5, 4.0 + ctx->M5, 0.0,
+                MIX_IDENTITY, par, 1, nullptr};
+        DWA_TRY(launch_hop(ctx, DWA_F64, h, nullptr));
+      }
+    }
+    DWA_TRY(launch_geta(ctx, geta, lt_b, lt_r, W[W_RES], W[W_PHI]));
+  }
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "adjoint sync");
+  if (stats) {
+    stats[0] = st[0];
+    stats[1] = st[1];
+  }
+  if (status == DWA_ENOCONV) set_error("forward or adjoint solve reached maxiter");
+  return status;
 }
 
 // Host-only access to the site-local matrices (no device needed); used to check

@@ -299,21 +299,36 @@ int launch_check_finite(dwa_ctx* ctx, const void* canon, size_t ncomplex, int* d
 
 // CGLS building blocks (templated on precision inside kernels.hip).  In update1, x
 // has storage xacc_prec(prec); the other fields have storage prec.
+// adj = true runs the updates of CGLS on D_bb^dag (premixes swapped; FP64 only).
 int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
-                      const void* q, const DevScalars* s, double* partials, int* nblocks);
+                      const void* q, const DevScalars* s, double* partials, int* nblocks,
+                      bool adj = false);
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
-                      const DevScalars* s);
+                      const DevScalars* s, bool adj = false);
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* partials_a, int na,
                        const double* partials_b, int nb);
 int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f);
+
+// gradient path (adjoint.hip), FP64 SoA fields; "lt" is g5 lambda
+int launch_adj_source(dwa_ctx* ctx, void* f_b, void* f_r, const void* eta_p);
+int launch_omega(dwa_ctx* ctx, void* ob, void* oc, const void* psi, const void* eta, int par);
+int launch_jpsi(dwa_ctx* ctx, void* out, const void* psi);
+int slice_dot_blocks(size_t per_slice);
+int launch_slice_dot(dwa_ctx* ctx, const void* a, const void* b, int nslices, size_t vh, bool g5,
+                     double* partials);
+int launch_force(dwa_ctx* ctx, void* gU, const void* lt_b, const void* lt_r, const void* ph_b,
+                 const void* ph_r);
+int launch_geta(dwa_ctx* ctx, void* geta, const void* lt_b, const void* lt_r, const void* dw_b,
+                const void* dw_r);
 
 // per-precision launchers (kcommon.h), instantiated in kernels_{f64,f32,bf16}.hip
 template <typename S> int launch_hop_p(dwa_ctx*, const HopOp&, int*);
 template <typename S> int launch_smix_p(dwa_ctx*, int, void*, const void*, const void*, double, int,
                                         double*, int*);
 template <typename S> int launch_update1_p(dwa_ctx*, void*, void*, void*, const void*, const void*,
-                                           const DevScalars*, double*, int*);
-template <typename S> int launch_update2_p(dwa_ctx*, void*, void*, const void*, const DevScalars*);
+                                           const DevScalars*, double*, int*, bool);
+template <typename S> int launch_update2_p(dwa_ctx*, void*, void*, const void*, const DevScalars*,
+                                           bool);
 template <typename S> int norm2_p(dwa_ctx*, const void*, size_t, double*, int*);
 template <typename S> int axpby_p(dwa_ctx*, void*, double, const void*, double, size_t);
 template <typename S> int zero_p(dwa_ctx*, void*, size_t);

@@ -658,8 +658,9 @@ __global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a
   __syncthreads();
 
   // phase 2: fifth-dimension mix.  Work items are (chirality, site, component of that
-  // chirality); PH is a whole number of wavefronts, so the chirality is the same on
-  // every lane of a wave and the branch on it is uniform.
+  // chirality); PH is a whole number of wavefronts and the block is launched in whole
+  // wavefronts, so the chirality is the same on every lane of a wave and the branch on
+  // it is uniform.
   double nrm = 0.0;
   constexpr int PH = ((NS * 6 + 63) / 64) * 64;
   for (int t = threadIdx.x; t < 2 * PH; t += blockDim.x) {
@@ -717,7 +718,7 @@ __global__ void __launch_bounds__(256) smix_kernel(typename S::elem* __restrict_
 }
 
 // CGLS update 1: x += a p ; r -= a q ; |r|^2 ; w = (g5 I^-T G^-1) r
-template <typename S, int LS, bool DENSE>
+template <typename S, int LS, bool DENSE, int PK>
 __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type::elem* __restrict__ x,
                                                          typename S::elem* __restrict__ r,
                                                          typename S::elem* __restrict__ w,
@@ -750,8 +751,8 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type:
           rv[j] = as_stored<S>(rr);  // premix the value as stored
           nrm += (double)norm2(rv[j]);
         }
-      if (ch == 0) apply_mix<R, LSM, MIX_G5_IINVT_GINV, 0, DENSE>(rv, Ls, P);
-      else apply_mix<R, LSM, MIX_G5_IINVT_GINV, 1, DENSE>(rv, Ls, P);
+      if (ch == 0) apply_mix<R, LSM, PK, 0, DENSE>(rv, Ls, P);
+      else apply_mix<R, LSM, PK, 1, DENSE>(rv, Ls, P);
 #pragma unroll
       for (int i = 0; i < LSM; ++i)
         if (i < Ls) st<S>(w, (size_t(i) * 12 + comp) * Vh + site, rv[i]);
@@ -761,7 +762,7 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type:
 }
 
 // CGLS update 2: p = z + beta p ; u = (B G) p
-template <typename S, int LS, bool DENSE>
+template <typename S, int LS, bool DENSE, int PK>
 __global__ void __launch_bounds__(256) cg_update2_kernel(typename S::elem* __restrict__ p,
                                                          typename S::elem* __restrict__ u,
                                                          const typename S::elem* __restrict__ z,
@@ -785,8 +786,8 @@ __global__ void __launch_bounds__(256) cg_update2_kernel(typename S::elem* __res
         st<S>(p, idx, v);
         pv[j] = as_stored<S>(v);
       }
-    if (ch == 0) apply_mix<R, LSM, MIX_BG, 0, DENSE>(pv, Ls, P);
-    else apply_mix<R, LSM, MIX_BG, 1, DENSE>(pv, Ls, P);
+    if (ch == 0) apply_mix<R, LSM, PK, 0, DENSE>(pv, Ls, P);
+    else apply_mix<R, LSM, PK, 1, DENSE>(pv, Ls, P);
 #pragma unroll
     for (int i = 0; i < LSM; ++i)
       if (i < Ls) st<S>(u, (size_t(i) * 12 + comp) * Vh + site, pv[i]);
@@ -990,7 +991,10 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
   const unsigned grid = (unsigned)((ctx->Vh + NS - 1) / NS);
   size_t shm = hop_mix_lds_bytes<RealOf<S>>(NS, Ls);
   if (shm < ctx->hop_min_lds) shm = ctx->hop_min_lds;
-  const dim3 block(NS * Ls);
+  // whole wavefronts: phase 2 hands each wave one chirality, which needs the work
+  // items of a wave to come from one 64-aligned range (the extra threads of the last
+  // wave idle in phase 1)
+  const dim3 block((NS * Ls + 63) / 64 * 64);
   const int mode = op.pre ? 2 : (op.post ? 1 : 0);
   if (op.pre && op.post) {
     set_error("hop with both pre and post terms is not supported");
@@ -1041,6 +1045,18 @@ int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* 
     return DWA_EINVAL;
   }
   const int grid = (int)((6u * (unsigned)ctx->Vh + 255) / 256);
+  if (mix == MIX_I_ALPHA) {  // the site-local block I of D_alpha: dense table, FP64 only
+    if constexpr (S::prec == DWA_F64) {
+      const MixTables T = mix_tables<S>(ctx, MIX_I_ALPHA);
+      hipLaunchKernelGGL((smix_kernel<S, 0, MIX_I_ALPHA, true>), dim3(grid), dim3(256), 0,
+                         ctx->stream, (double2*)out, (const double2*)in, (const double2*)post,
+                         post_coef, T, ctx->Ls, (unsigned)ctx->Vh, partials);
+      if (nblocks_out) *nblocks_out = grid;
+      return hip_fail(hipGetLastError(), "smix kernel launch");
+    }
+    set_error("site-local I_1 G runs in FP64 only");
+    return DWA_EINVAL;
+  }
   if (mix == MIX_BG) launch_smix_k<S, MIX_BG>(ctx, out, in, post, post_coef, partials, grid);
   else if (mix == MIX_N) launch_smix_k<S, MIX_N>(ctx, out, in, post, post_coef, partials, grid);
   else if (mix == MIX_G5_IINVT_GINV)
@@ -1055,15 +1071,29 @@ int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* 
 
 template <typename S>
 int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, const void* q,
-                     const DevScalars* s, double* partials, int* nblocks) {
+                     const DevScalars* s, double* partials, int* nblocks, bool adj) {
   using E = typename S::elem;
   using EX = typename XAcc<S>::type::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
   const int grid = (int)((6u * Vh + 255) / 256);
-  const MixTables T = mix_tables<S>(ctx, MIX_G5_IINVT_GINV);
-#define DWA_U1(LSV, DV)                                                                         \
-  hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV>), dim3(grid), dim3(256), 0, ctx->stream,    \
-                     (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T, ctx->Ls, Vh, partials)
+  if (adj && S::prec != DWA_F64) {
+    set_error("CGLS on D_bb^dag runs in FP64 only");
+    return DWA_EINVAL;
+  }
+  // w is the premixed input of the operator applied to r next: D_bb^dag (normal CGLS)
+  // or, for CGLS on D_bb^dag, D_bb
+  const MixTables T = mix_tables<S>(ctx, adj ? MIX_BG : MIX_G5_IINVT_GINV);
+#define DWA_U1(LSV, DV)                                                                          \
+  if (adj) {                                                                                     \
+    if constexpr (S::prec == DWA_F64)                                                            \
+      hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_BG>), dim3(grid), dim3(256), 0,      \
+                         ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,       \
+                         ctx->Ls, Vh, partials);                                                 \
+  } else {                                                                                       \
+    hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid), dim3(256), \
+                       0, ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,      \
+                       ctx->Ls, Vh, partials);                                                   \
+  }
   DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_U1)
 #undef DWA_U1
   if (nblocks) *nblocks = grid;
@@ -1071,14 +1101,26 @@ int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, con
 }
 
 template <typename S>
-int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevScalars* s) {
+int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevScalars* s, bool adj) {
   using E = typename S::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
   const int grid = (int)((6u * Vh + 255) / 256);
-  const MixTables T = mix_tables<S>(ctx, MIX_BG);
-#define DWA_U2(LSV, DV)                                                                      \
-  hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV>), dim3(grid), dim3(256), 0, ctx->stream, \
-                     (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh)
+  if (adj && S::prec != DWA_F64) {
+    set_error("CGLS on D_bb^dag runs in FP64 only");
+    return DWA_EINVAL;
+  }
+  // u is the premixed input of the operator applied to p next: D_bb (normal CGLS) or,
+  // for CGLS on D_bb^dag, D_bb^dag
+  const MixTables T = mix_tables<S>(ctx, adj ? MIX_G5_IINVT_GINV : MIX_BG);
+#define DWA_U2(LSV, DV)                                                                        \
+  if (adj) {                                                                                   \
+    if constexpr (S::prec == DWA_F64)                                                          \
+      hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid),       \
+                         dim3(256), 0, ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh); \
+  } else {                                                                                     \
+    hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_BG>), dim3(grid), dim3(256), 0,       \
+                       ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh);              \
+  }
   DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_U2)
 #undef DWA_U2
   return hip_fail(hipGetLastError(), "cg update2 launch");
@@ -1140,8 +1182,8 @@ int convert_p(dwa_ctx* ctx, void* out, const void* in, size_t n, double scale) {
   template int launch_smix_p<S>(dwa_ctx*, int, void*, const void*, const void*, double, int,    \
                                 double*, int*);                                                 \
   template int launch_update1_p<S>(dwa_ctx*, void*, void*, void*, const void*, const void*,     \
-                                   const DevScalars*, double*, int*);                           \
-  template int launch_update2_p<S>(dwa_ctx*, void*, void*, const void*, const DevScalars*);     \
+                                   const DevScalars*, double*, int*, bool);                     \
+  template int launch_update2_p<S>(dwa_ctx*, void*, void*, const void*, const DevScalars*, bool); \
   template int norm2_p<S>(dwa_ctx*, const void*, size_t, double*, int*);                        \
   template int axpby_p<S>(dwa_ctx*, void*, double, const void*, double, size_t);                \
   template int zero_p<S>(dwa_ctx*, void*, size_t);                                              \

@@ -187,12 +187,12 @@ int launch_smix(dwa_ctx* ctx, int prec, int mix, void* out, const void* in, cons
                                        nblocks_out));
 }
 int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
-                      const void* q, const DevScalars* s, double* partials, int* nblocks) {
-  DWA_DISPATCH(prec, launch_update1_p<S_>(ctx, x, r, w, p, q, s, partials, nblocks));
+                      const void* q, const DevScalars* s, double* partials, int* nblocks, bool adj) {
+  DWA_DISPATCH(prec, launch_update1_p<S_>(ctx, x, r, w, p, q, s, partials, nblocks, adj));
 }
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
-                      const DevScalars* s) {
-  DWA_DISPATCH(prec, launch_update2_p<S_>(ctx, p, u, z, s));
+                      const DevScalars* s, bool adj) {
+  DWA_DISPATCH(prec, launch_update2_p<S_>(ctx, p, u, z, s, adj));
 }
 int launch_norm2(dwa_ctx* ctx, int prec, const void* x, size_t n, double* partials, int* nblocks) {
   DWA_DISPATCH(prec, norm2_p<S_>(ctx, x, n, partials, nblocks));

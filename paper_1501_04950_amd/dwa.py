@@ -91,6 +91,9 @@ def lib():
         "dwa_set_alpha": (c_int, [P, c_double]),
         "dwa_alpha_sweep": (c_int, [P, POINTER(c_double), c_int, P, P, POINTER(dwa_solve_opts),
                                     POINTER(dwa_solve_stats)]),
+        "dwa_propagator_adjoint": (c_int, [P, P, P, POINTER(c_double), POINTER(c_double),
+                                           POINTER(c_double), POINTER(c_double), P, P, P,
+                                           POINTER(dwa_solve_opts), POINTER(dwa_solve_stats)]),
         "dwa_strerror": (ctypes.c_char_p, [c_int]),
         "dwa_last_error": (ctypes.c_char_p, []),
         "dwa_debug_smatrix": (c_int, [POINTER(dwa_params), c_int, POINTER(c_double)]),
@@ -295,6 +298,41 @@ class Context:
         if want_psi:
             return y1, st.as_dict(), rc, psi
         return y1, st.as_dict(), rc
+
+    def propagator_adjoint(self, eta, eta_prime, want=("U", "eta", "alpha", "b", "c"), **kw):
+        """Gradients of L = Re <eta', y_1> (dwa_propagator_adjoint).  Returns a dict with
+        the requested entries of 'U' [4, V, 3, 3], 'eta' [V, 4, 3] (device complex128),
+        'alpha' (float), 'b', 'c' (numpy [Ls]) plus 'L', 'y1', 'stats' and 'status'."""
+        torch = _torch()
+        self._check_canon(eta, (self.V, 4, 3))
+        self._check_canon(eta_prime, (self.V, 4, 3))
+        dev = self.device
+        gU = torch.zeros((4, self.V, 3, 3), dtype=torch.complex128, device=dev) if "U" in want else None
+        geta = torch.zeros((self.V, 4, 3), dtype=torch.complex128, device=dev) if "eta" in want else None
+        ga = c_double(0.0)
+        gb = np.zeros(self.Ls) if "b" in want else None
+        gc = np.zeros(self.Ls) if "c" in want else None
+        L = c_double(0.0)
+        y1 = torch.zeros((self.V, 4, 3), dtype=torch.complex128, device=dev)
+        o = self.opts(**kw)
+        st = (dwa_solve_stats * 2)()
+        dp = lambda a: a.ctypes.data_as(POINTER(c_double)) if a is not None else None
+        rc = check(lib().dwa_propagator_adjoint(
+            self._h, _ptr(gU) if gU is not None else None, _ptr(geta) if geta is not None else None,
+            byref(ga) if "alpha" in want else None, dp(gb), dp(gc), byref(L), _ptr(y1),
+            _ptr(eta), _ptr(eta_prime), byref(o), st), allow=(DWA_ENOCONV,))
+        out = {"L": L.value, "y1": y1, "stats": [st[0].as_dict(), st[1].as_dict()], "status": rc}
+        if gU is not None:
+            out["U"] = gU
+        if geta is not None:
+            out["eta"] = geta
+        if "alpha" in want:
+            out["alpha"] = ga.value
+        if gb is not None:
+            out["b"] = gb
+        if gc is not None:
+            out["c"] = gc
+        return out
 
     def set_alpha(self, alpha):
         check(lib().dwa_set_alpha(self._h, float(alpha)))

@@ -61,6 +61,8 @@ def test_calls_reject_null_context():
     L = dwa.lib()
     assert L.dwa_set_alpha(None, 0.5) == dwa.DWA_EINVAL
     assert L.dwa_alpha_sweep(None, None, 1, None, None, None, None) == dwa.DWA_EINVAL
+    assert L.dwa_propagator_adjoint(None, None, None, None, None, None, None, None, None, None,
+                                    None, None) == dwa.DWA_EINVAL
     assert L.dwa_apply_Dbb(None, 0, None, None) == dwa.DWA_EINVAL
     assert L.dwa_set_links(None, None) == dwa.DWA_EINVAL
     assert L.dwa_propagator(None, None, None, None, None, None) == dwa.DWA_EINVAL

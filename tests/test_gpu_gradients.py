@@ -1,0 +1,164 @@
+"""GPU gradients of L = Re <eta', y_1> (dwa_propagator_adjoint) against the oracle's
+adjoint-state gradients (small lattices) and against central finite differences of
+GPU solves on the 8^4, Ls = 8 workload."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import adjoint, redblack
+from oracle.gamma import GAMMA5, spin_apply
+from paper_1501_04950_amd import dwa, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("dims,Ls", [((2, 2, 2, 4), 4), ((4, 2, 2, 4), 5)])
+def test_gradients_match_oracle(dims, Ls):
+    """Every gradient against the oracle (unpreconditioned adjoint solve, literal block
+    terms) with per-slice b_i, c_i without symmetry; both solves at 1e-13."""
+    dev = gpu()
+    rng = np.random.default_rng(21 + Ls)
+    b, c = rng.uniform(1.0, 2.0, Ls), rng.uniform(0.1, 0.9, Ls)
+    U = synth.su3_field(dims, 0.5, 31 + Ls)
+    p = redblack.Params.make(dims, Ls, -1.8, 0.1, 0.8, b, c)
+    eta = synth.gaussian_source(dims, 41)
+    eta_p = synth.gaussian_source(dims, 42)
+    ref = adjoint.gradients(U, eta, eta_p, p, tol=1e-13)
+    L_ref = adjoint.loss(U, eta, eta_p, p)
+    say(f"[gpu] gradients {dims} Ls={Ls}")
+    ctx = dwa.Context(dims, Ls, -1.8, 0.1, 0.8, b, c)
+    ctx.set_links(torch.from_numpy(U).to(dev))
+    g = ctx.propagator_adjoint(torch.from_numpy(eta).to(dev), torch.from_numpy(eta_p).to(dev),
+                               tol=1e-13, check_every=1)
+    say(f"    L gpu {g['L']:.15e} oracle {L_ref:.15e}; iters fwd {g['stats'][0]['iters']} "
+        f"adj {g['stats'][1]['iters']} adj resid {g['stats'][1]['rel_resid']:.1e}")
+    assert g["status"] == dwa.DWA_OK
+    assert g["stats"][1]["rel_resid"] <= 1e-12
+    assert abs(g["L"] - L_ref) <= 1e-11 * abs(L_ref)
+    errs = {"U": rel(g["U"].cpu().numpy(), ref["U"]), "eta": rel(g["eta"].cpu().numpy(), ref["eta"]),
+            "b": rel(g["b"], ref["b"]), "c": rel(g["c"], ref["c"])}
+    say(f"    rel errors {errs}; alpha gpu {g['alpha']:.2e} oracle {ref['alpha']:.2e}")
+    for k, e in errs.items():
+        assert e < 1e-9, (k, e)
+    assert abs(g["alpha"]) <= 1e-9 * abs(L_ref)
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def c5():
+    name = "c5_8x8x8x8_ls8"
+    w = synth.WORKLOADS[name]
+    dev = gpu()
+    U = synth.workload_links(name)
+    eta = synth.gaussian_source(w["dims"], 51)
+    eta_p = synth.gaussian_source(w["dims"], 52)
+    alpha = w["alphas"][0]
+    ctx = dwa.Context(w["dims"], w["Ls"], w["M5"], w["m"], alpha, w["b"], w["c"])
+    Ud = torch.from_numpy(U).to(dev)
+    ctx.set_links(Ud)
+    e, ep = torch.from_numpy(eta).to(dev), torch.from_numpy(eta_p).to(dev)
+    say("[gpu] c5 adjoint gradients")
+    g = ctx.propagator_adjoint(e, ep, tol=1e-13, check_every=5)
+    assert g["status"] == dwa.DWA_OK
+    yield dict(w=w, U=U, Ud=Ud, eta=e, eta_p=ep, ctx=ctx, g=g, alpha=alpha)
+    ctx.close()
+
+
+def _loss(ctx, eta, eta_p):
+    y, st, rc = ctx.propagator(eta, tol=1e-13, check_every=5)
+    assert rc == dwa.DWA_OK
+    return float(torch.sum(torch.conj(eta_p) * y).real)
+
+
+def _close(fd, adj, L):
+    assert abs(fd - adj) <= 1e-6 * max(abs(adj), abs(L)), (fd, adj)
+
+
+def test_c5_link_gradient_finite_differences(c5):
+    """16 random complex link directions, central differences with step 1e-6."""
+    ctx, g, Ud = c5["ctx"], c5["g"], c5["Ud"]
+    gen = torch.Generator(device="cpu").manual_seed(61)
+    L = g["L"]
+    for k in range(16):
+        d = torch.complex(torch.randn(Ud.shape, generator=gen, dtype=torch.float64),
+                          torch.randn(Ud.shape, generator=gen, dtype=torch.float64)).to(Ud.device)
+        vals = []
+        for sgn in (1.0, -1.0):
+            ctx.set_links((Ud + sgn * 1e-6 * d).contiguous())
+            vals.append(_loss(ctx, c5["eta"], c5["eta_p"]))
+        fd = (vals[0] - vals[1]) / 2e-6
+        adj = float(torch.sum(torch.conj(g["U"]) * d).real)
+        say(f"    link dir {k}: fd {fd:.9e} adjoint {adj:.9e}")
+        _close(fd, adj, L)
+    ctx.set_links(Ud)
+
+
+def test_c5_coefficient_and_alpha_gradients_finite_differences(c5):
+    """8 directions in (b, c) and 8 in (alpha, b): new contexts for b and c, set_alpha
+    for alpha.  dL/dalpha itself is zero (y_1 does not depend on alpha)."""
+    w, g = c5["w"], c5["g"]
+    Ls = w["Ls"]
+    rng = np.random.default_rng(71)
+    b0, c0 = np.full(Ls, w["b"]), np.full(Ls, w["c"])
+    L = g["L"]
+
+    def loss_at(b, c, alpha):
+        ctx = dwa.Context(w["dims"], Ls, w["M5"], w["m"], alpha, b, c)
+        ctx.set_links(c5["Ud"])
+        v = _loss(ctx, c5["eta"], c5["eta_p"])
+        ctx.close()
+        return v
+
+    for k in range(8):
+        db, dc = rng.normal(size=Ls), rng.normal(size=Ls)
+        fd = (loss_at(b0 + 1e-6 * db, c0 + 1e-6 * dc, c5["alpha"])
+              - loss_at(b0 - 1e-6 * db, c0 - 1e-6 * dc, c5["alpha"])) / 2e-6
+        adj = float(g["b"] @ db + g["c"] @ dc)
+        say(f"    (b, c) dir {k}: fd {fd:.9e} adjoint {adj:.9e}")
+        _close(fd, adj, L)
+    for k in range(8):
+        da, db = rng.normal(), rng.normal(size=Ls)
+        fd = (loss_at(b0 + 1e-6 * db, c0, c5["alpha"] + 1e-6 * da)
+              - loss_at(b0 - 1e-6 * db, c0, c5["alpha"] - 1e-6 * da)) / 2e-6
+        adj = float(g["alpha"] * da + g["b"] @ db)
+        say(f"    (alpha, b) dir {k}: fd {fd:.9e} adjoint {adj:.9e}")
+        _close(fd, adj, L)
+    assert abs(g["alpha"]) <= 1e-8 * abs(L)
+
+
+def test_c5_source_gradient(c5):
+    """dL/deta against finite differences and against g5 y_1[g5 eta'] (b, c constant,
+    so the 4D operator is g5-Hermitian)."""
+    ctx, g = c5["ctx"], c5["g"]
+    gen = torch.Generator(device="cpu").manual_seed(81)
+    eta = c5["eta"]
+    for k in range(4):
+        d = torch.complex(torch.randn(eta.shape, generator=gen, dtype=torch.float64),
+                          torch.randn(eta.shape, generator=gen, dtype=torch.float64)).to(eta.device)
+        fd = (_loss(ctx, (eta + 1e-6 * d).contiguous(), c5["eta_p"])
+              - _loss(ctx, (eta - 1e-6 * d).contiguous(), c5["eta_p"])) / 2e-6
+        adj = float(torch.sum(torch.conj(g["eta"]) * d).real)
+        _close(fd, adj, g["L"])
+    g5 = torch.from_numpy(np.diag(GAMMA5).real.copy()).to(eta.device)[None, :, None]
+    y5, _, rc = ctx.propagator((g5 * c5["eta_p"]).contiguous(), tol=1e-13, check_every=5)
+    r = float(torch.linalg.vector_norm(g["eta"] - g5 * y5) / torch.linalg.vector_norm(g["eta"]))
+    say(f"    g5 identity rel diff {r:.2e}")
+    assert r < 1e-9

@@ -24,6 +24,7 @@ CASES = {
     "ragged_2x2x2x6_ls2": ((2, 2, 2, 6), 2, -1.7, 0.2, 1.3, None, None),
     "c1_4x4x4x4_ls8": ((4, 4, 4, 4), 8, -1.8, 0.05, 0.8, 1.5, 0.5),
     "lsmax32_4x2x2x4_ls20": ((4, 2, 2, 4), 20, -1.6, 0.03, 0.9, None, None),
+    "odd_4x2x2x4_ls5": ((4, 2, 2, 4), 5, -1.8, 0.1, 0.8, None, None),
     "c2_8x8x8x16_ls12": ((8, 8, 8, 16), 12, -1.8, 0.02, 0.6, 1.5, 0.5),
 }
 
