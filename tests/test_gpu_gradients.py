@@ -162,3 +162,42 @@ def test_c5_source_gradient(c5):
     r = float(torch.linalg.vector_norm(g["eta"] - g5 * y5) / torch.linalg.vector_norm(g["eta"]))
     say(f"    g5 identity rel diff {r:.2e}")
     assert r < 1e-9
+
+
+def test_autograd_function(c5):
+    """The differentiable propagator: for L = Re <eta', y_1> its backward gives the
+    library's adjoint gradients; for the nonlinear L2 = |y_1|^2 a link direction agrees
+    with central differences."""
+    from paper_1501_04950_amd import autograd as dag
+    w, ctx, g = c5["w"], c5["ctx"], c5["g"]
+    dev = c5["Ud"].device
+    U = c5["Ud"].clone().requires_grad_(True)
+    eta = c5["eta"].clone().requires_grad_(True)
+    alpha = torch.tensor(c5["alpha"], dtype=torch.float64, device=dev, requires_grad=True)
+    b = torch.full((w["Ls"],), w["b"], dtype=torch.float64, device=dev, requires_grad=True)
+    c = torch.full((w["Ls"],), w["c"], dtype=torch.float64, device=dev, requires_grad=True)
+    y = dag.propagator(ctx, U, eta, alpha, b, c, tol=1e-13, check_every=5)
+    L = torch.sum(torch.conj(c5["eta_p"]) * y).real
+    L.backward()
+    assert rel(U.grad.cpu().numpy(), g["U"].cpu().numpy()) < 1e-10
+    assert rel(eta.grad.cpu().numpy(), g["eta"].cpu().numpy()) < 1e-10
+    assert rel(b.grad.cpu().numpy(), g["b"]) < 1e-10 and rel(c.grad.cpu().numpy(), g["c"]) < 1e-10
+    assert abs(float(alpha.grad)) <= 1e-8 * abs(float(L))
+
+    U2 = c5["Ud"].clone().requires_grad_(True)
+    y2 = dag.propagator(ctx, U2, c5["eta"], tol=1e-13, check_every=5)
+    L2 = torch.sum(torch.abs(y2) ** 2)
+    L2.backward()
+    gen = torch.Generator(device="cpu").manual_seed(91)
+    d = torch.complex(torch.randn(U2.shape, generator=gen, dtype=torch.float64),
+                      torch.randn(U2.shape, generator=gen, dtype=torch.float64)).to(dev)
+    vals = []
+    for sgn in (1.0, -1.0):
+        ctx.set_links((c5["Ud"] + sgn * 1e-6 * d).contiguous())
+        yy, _, _ = ctx.propagator(c5["eta"], tol=1e-13, check_every=5)
+        vals.append(float(torch.sum(torch.abs(yy) ** 2)))
+    ctx.set_links(c5["Ud"])
+    fd = (vals[0] - vals[1]) / 2e-6
+    adj = float(torch.sum(torch.conj(U2.grad) * d).real)
+    say(f"    |y|^2 link dir: fd {fd:.9e} autograd {adj:.9e}")
+    _close(fd, adj, float(L2))
