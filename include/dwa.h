@@ -214,6 +214,40 @@ int dwa_propagator_adjoint(dwa_ctx *ctx, void *gU, void *geta, double *galpha, d
                            const void *eta_prime, const dwa_solve_opts *opts,
                            dwa_solve_stats *stats);
 
+/* Batches of right-hand sides (the paper's solves are 12 spin-colour sources per gauge
+ * field, Sec. 3).  dwa_reserve_batch allocates the workspace for up to nmax fields of
+ * this context (17 FP64 and 17 low-precision half fields per entry) and a
+ * stream of its own; it replaces an earlier reservation.  Batched solves allocate
+ * nothing. */
+int dwa_reserve_batch(dwa_ctx *ctx, int nmax);
+
+/* out = D_bb in for nrhs black SoA fields of precision prec stored back to back (one
+ * batched launch per kernel; uses the batch workspace, nrhs <= the reservation).
+ * out_norm2 (host, nrhs doubles, may be NULL) receives |out|^2 per field from the
+ * kernel's own partial sums (the CGNE reduction). */
+int dwa_apply_Dbb_batch(dwa_ctx *ctx, int prec, int nrhs, void *out, const void *in,
+                        double *out_norm2);
+
+/* y_1 for nrhs sources at once: eta and y1 hold nrhs canonical complex128 [V][4][3]
+ * fields back to back (device).  Every field takes the path of dwa_propagator; the
+ * batch shares each kernel launch (the fused hop reads a chunk's links once per XCD for
+ * all fields), and the CGNE iteration body is replayed from a hipGraph between host
+ * convergence checks.  opts->inner_prec = DWA_F64 runs FP64 CGNE; DWA_F32 / DWA_BF16
+ * run FP64 defect correction around batched low-precision CGNE (opts->mixed_mode is
+ * not used).  stats (may be NULL) receives nrhs entries.  nrhs must not exceed the
+ * reservation.  Returns DWA_ENOCONV if any field missed the tolerance. */
+int dwa_propagator_batch(dwa_ctx *ctx, int nrhs, void *y1, const void *eta,
+                         const dwa_solve_opts *opts, dwa_solve_stats *stats);
+
+/* dwa_propagator_batch over several contexts (lattices of different sizes) in one
+ * solve: nrhs[i] sources of ctxs[i] in eta[i] -> y1[i]; one hipGraph holds the CGNE
+ * iteration of every context.  All contexts must be on one device and have reserved
+ * their batches; the work runs on the first context's batch stream after every
+ * context's stream has drained.  stats receives sum(nrhs) entries in context order. */
+int dwa_propagator_multi(dwa_ctx *const *ctxs, int nctx, const int *nrhs, void *const *y1,
+                         const void *const *eta, const dwa_solve_opts *opts,
+                         dwa_solve_stats *stats);
+
 const char *dwa_strerror(int status);
 const char *dwa_last_error(void);
 

@@ -73,25 +73,25 @@ bool valid_prec(int prec) { return prec == DWA_F64 || prec == DWA_F32 || prec ==
 
 // out = in - 1/4 G^-1 I^-1 H_br N H_rb (B G in); u is the premixed input B G in.
 int dbb_from_premix(dwa_ctx* ctx, int prec, void* out, const void* in, const void* u, void* tr,
-                    double* partials, int* nblocks) {
-  HopOp a{u, tr, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_N, 1, ctx->Ls, nullptr};
+                    double* partials, int* nblocks, int nrhs = 1) {
+  HopOp a{u, tr, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_N, 1, ctx->Ls, nullptr, nrhs};
   DWA_TRY(launch_hop(ctx, prec, a, nullptr));
-  HopOp b{tr, out, nullptr, in, -0.25, 0.0, 1.0, MIX_GINV_IINV, 0, ctx->Ls, partials};
+  HopOp b{tr, out, nullptr, in, -0.25, 0.0, 1.0, MIX_GINV_IINV, 0, ctx->Ls, partials, nrhs};
   return launch_hop(ctx, prec, b, nblocks);
 }
 
 // out = in - 1/4 G B^T g5 H_br N^T H_rb w; w is the premixed input g5 I^-T G^-1 in.
 int dbbdag_from_premix(dwa_ctx* ctx, int prec, void* out, const void* in, const void* w, void* tr,
-                       double* partials, int* nblocks) {
-  HopOp a{w, tr, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_NT, 1, ctx->Ls, nullptr};
+                       double* partials, int* nblocks, int nrhs = 1) {
+  HopOp a{w, tr, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_NT, 1, ctx->Ls, nullptr, nrhs};
   DWA_TRY(launch_hop(ctx, prec, a, nullptr));
-  HopOp b{tr, out, nullptr, in, -0.25, 0.0, 1.0, MIX_G_BT_G5, 0, ctx->Ls, partials};
+  HopOp b{tr, out, nullptr, in, -0.25, 0.0, 1.0, MIX_G_BT_G5, 0, ctx->Ls, partials, nrhs};
   return launch_hop(ctx, prec, b, nblocks);
 }
 
-int apply_dbb(dwa_ctx* ctx, int prec, void* out, const void* in, void* tb, void* tr) {
-  DWA_TRY(launch_smix(ctx, prec, MIX_BG, tb, in, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
-  return dbb_from_premix(ctx, prec, out, in, tb, tr, nullptr, nullptr);
+int apply_dbb(dwa_ctx* ctx, int prec, void* out, const void* in, void* tb, void* tr, int nrhs = 1) {
+  DWA_TRY(launch_smix(ctx, prec, MIX_BG, tb, in, nullptr, 0.0, ctx->Ls, nullptr, nullptr, nrhs));
+  return dbb_from_premix(ctx, prec, out, in, tb, tr, nullptr, nullptr, nrhs);
 }
 
 int apply_dbbdag(dwa_ctx* ctx, int prec, void* out, const void* in, void* tb, void* tr) {
@@ -494,6 +494,243 @@ int check_ctx(dwa_ctx* ctx) {
   return DWA_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batches: nrhs fields of one context stored back to back (field_elems apart).
+
+void free_batch(dwa_ctx* ctx) {
+  BatchWs& b = ctx->batch;
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  for (auto p : b.f64) f(p);
+  for (auto& row : b.lo)
+    for (auto p : row) f(p);
+  f(b.xacc);
+  f(b.d_scal);
+  f(b.partials);
+  f(b.d_coef);
+  if (b.h_scal) (void)hipHostFree(b.h_scal);
+  if (b.h_coef) (void)hipHostFree(b.h_coef);
+  if (b.h_active) (void)hipHostFree(b.h_active);
+  if (b.stream) (void)hipStreamDestroy(b.stream);
+  b = BatchWs{};
+}
+
+double* bbank(dwa_ctx* ctx, int i) {
+  return ctx->batch.partials + size_t(i) * ctx->batch.nmax * ctx->batch.bank_elems;
+}
+
+// One batched CGLS system: nr fields of one context, all in storage precision prec.
+struct BatchSys {
+  dwa_ctx* ctx = nullptr;
+  int nr = 0;
+  int prec = DWA_F64;
+  void* x = nullptr;          // solution (storage xacc_prec(prec))
+  const void* rhs = nullptr;  // right-hand sides
+  void *r = nullptr, *p = nullptr, *z = nullptr, *q = nullptr, *w = nullptr, *u = nullptr,
+       *t = nullptr;
+  std::vector<double> tol;    // per field; a field with tol < 0 starts frozen
+  std::vector<int> iters, converged, breakdown;
+  long long n_dbb = 0;
+};
+
+void batch_sys_vectors(BatchSys& b) {
+  BatchWs& w = b.ctx->batch;
+  if (b.prec == DWA_F64) {
+    b.r = w.f64[B_R]; b.p = w.f64[B_P]; b.z = w.f64[B_Z]; b.q = w.f64[B_Q];
+    b.w = w.f64[B_W]; b.u = w.f64[B_U]; b.t = w.f64[B_T];
+  } else {
+    void** L = w.lo[b.prec];
+    b.r = L[BL_R]; b.p = L[BL_P]; b.z = L[BL_Z]; b.q = L[BL_Q];
+    b.w = L[BL_W]; b.u = L[BL_U]; b.t = L[BL_T];
+  }
+}
+
+// Freeze field k of a system (host-driven: the finalize kernel then keeps x and r).
+int batch_freeze(BatchSys& b, int k, hipStream_t st) {
+  BatchWs& w = b.ctx->batch;
+  w.h_active[k] = 0;
+  DWA_HIP(hipMemcpyAsync(&w.d_scal[k].active, &w.h_active[k], sizeof(int), hipMemcpyHostToDevice, st),
+          "active flag");
+  return DWA_OK;
+}
+
+// One CGLS iteration of every system (the body that is captured into a hipGraph).
+int batch_iteration(std::vector<BatchSys>& S) {
+  for (auto& b : S) {
+    dwa_ctx* ctx = b.ctx;
+    DevScalars* sc = ctx->batch.d_scal;
+    int nbA = 0, nbB = 0, nbZ = 0;
+    DWA_TRY(dbb_from_premix(ctx, b.prec, b.q, b.p, b.u, b.t, bbank(ctx, 0), &nbA, b.nr));
+    DWA_TRY(launch_cg_finalize(ctx, 0, sc, bbank(ctx, 0), nbA, nullptr, 0, b.nr));
+    DWA_TRY(launch_cg_update1(ctx, b.prec, b.x, b.r, b.w, b.p, b.q, sc, bbank(ctx, 1), &nbB, false, b.nr));
+    DWA_TRY(dbbdag_from_premix(ctx, b.prec, b.z, b.r, b.w, b.t, bbank(ctx, 0), &nbZ, b.nr));
+    DWA_TRY(launch_cg_finalize(ctx, 1, sc, bbank(ctx, 0), nbZ, bbank(ctx, 1), nbB, b.nr));
+    DWA_TRY(launch_cg_update2(ctx, b.prec, b.p, b.u, b.z, sc, false, b.nr));
+    b.n_dbb += 2LL * b.nr;
+  }
+  return DWA_OK;
+}
+
+// CGLS on every field of every system at once.  All work runs on stream st (the
+// contexts' streams point at it for the duration).  Between host checks the iteration
+// body of all systems is replayed from one hipGraph (no memset nodes: kernels only).
+// A field stops (is frozen on the device) when its recursive residual reaches its
+// tolerance; iteration counts are those of the check at which it stopped.
+int cgls_multi(std::vector<BatchSys>& S, hipStream_t st, int maxiter, int check_every,
+               bool use_graph) {
+  if (check_every < 1) check_every = 1;
+  for (auto& b : S) {
+    dwa_ctx* ctx = b.ctx;
+    const size_t n = field_elems(ctx);
+    DevScalars* sc = ctx->batch.d_scal;
+    int nbA = 0, nbB = 0;
+    b.iters.assign(b.nr, 0);
+    b.converged.assign(b.nr, 0);
+    b.breakdown.assign(b.nr, 0);
+    DWA_TRY(launch_zero(ctx, xacc_prec(b.prec), b.x, n, b.nr));
+    DWA_TRY(launch_axpby(ctx, b.prec, b.r, 1.0, b.rhs, 0.0, n, b.nr));
+    DWA_TRY(launch_smix(ctx, b.prec, MIX_G5_IINVT_GINV, b.w, b.r, nullptr, 0.0, ctx->Ls, nullptr, nullptr, b.nr));
+    DWA_TRY(dbbdag_from_premix(ctx, b.prec, b.z, b.r, b.w, b.t, bbank(ctx, 0), &nbA, b.nr));
+    DWA_TRY(launch_norm2(ctx, b.prec, b.rhs, n, bbank(ctx, 1), &nbB, b.nr));
+    DWA_TRY(launch_cg_finalize(ctx, 2, sc, bbank(ctx, 0), nbA, bbank(ctx, 1), nbB, b.nr));
+    DWA_TRY(launch_axpby(ctx, b.prec, b.p, 1.0, b.z, 0.0, n, b.nr));
+    DWA_TRY(launch_smix(ctx, b.prec, MIX_BG, b.u, b.p, nullptr, 0.0, ctx->Ls, nullptr, nullptr, b.nr));
+    b.n_dbb = b.nr;
+    for (int k = 0; k < b.nr; ++k) {
+      ctx->batch.h_active[k] = 1;
+      if (b.tol[k] < 0.0) {
+        DWA_TRY(batch_freeze(b, k, st));
+        b.converged[k] = 1;
+      }
+    }
+  }
+  if (std::getenv("DWA_BATCH_NO_GRAPH")) use_graph = false;  // eager replay (diagnostics)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  };
+  if (use_graph) {
+    DWA_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+    const int rc = batch_iteration(S);
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc != DWA_OK) {
+      cleanup();
+      return rc;
+    }
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_fail(e, "end capture");
+    }
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      cleanup();
+      return hip_fail(ei, "graph instantiate");
+    }
+    // the capture counted one iteration per system; the replays count themselves
+    for (auto& b : S) b.n_dbb -= 2LL * b.nr;
+  }
+  int k = 0;
+  for (;;) {
+    // host check: read every system's scalars
+    int active = 0;
+    for (auto& b : S) {
+      BatchWs& w = b.ctx->batch;
+      const hipError_t e = hipMemcpyAsync(w.h_scal, w.d_scal, sizeof(DevScalars) * b.nr,
+                                          hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "batch scalar readback");
+      }
+    }
+    {
+      const hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "batch sync");
+      }
+    }
+    for (auto& b : S) {
+      BatchWs& w = b.ctx->batch;
+      for (int f = 0; f < b.nr; ++f) {
+        if (!w.h_active[f]) continue;
+        const DevScalars& h = w.h_scal[f];
+        bool stop = false;
+        if (h.flags) {
+          b.breakdown[f] = 1;
+          stop = true;
+        } else if (h.b2 == 0.0 || h.rr <= b.tol[f] * b.tol[f] * h.b2) {
+          b.converged[f] = 1;
+          stop = true;
+        }
+        if (stop) {
+          b.iters[f] = k;
+          int rc = batch_freeze(b, f, st);
+          if (rc != DWA_OK) {
+            cleanup();
+            return rc;
+          }
+        } else {
+          ++active;
+        }
+      }
+    }
+    if (active == 0 || k >= maxiter) break;
+    const int nrun = std::min(check_every, maxiter - k);
+    for (int i = 0; i < nrun; ++i) {
+      if (exec) {
+        const hipError_t e = hipGraphLaunch(exec, st);
+        if (e != hipSuccess) {
+          cleanup();
+          return hip_fail(e, "graph launch");
+        }
+        for (auto& b : S) b.n_dbb += 2LL * b.nr;
+      } else {
+        const int rc = batch_iteration(S);
+        if (rc != DWA_OK) {
+          cleanup();
+          return rc;
+        }
+      }
+    }
+    k += nrun;
+  }
+  for (auto& b : S)
+    for (int f = 0; f < b.nr; ++f)
+      if (b.ctx->batch.h_active[f]) b.iters[f] = k;  // stopped by maxiter
+  cleanup();
+  return DWA_OK;
+}
+
+// Per-field |v|^2 of a batch (synchronising on st).
+int batch_norms(dwa_ctx* ctx, int prec, const void* v, int nr, hipStream_t st, double* out) {
+  int nb = 0;
+  DWA_TRY(launch_norm2(ctx, prec, v, field_elems(ctx), bbank(ctx, 3), &nb, nr));
+  std::vector<double> h(size_t(nb) * nr);
+  DWA_HIP(hipMemcpyAsync(h.data(), bbank(ctx, 3), sizeof(double) * h.size(), hipMemcpyDeviceToHost, st),
+          "batch norm readback");
+  DWA_HIP(hipStreamSynchronize(st), "batch norm sync");
+  for (int f = 0; f < nr; ++f) {
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) acc += h[size_t(f) * nb + i];
+    out[f] = acc;
+  }
+  return DWA_OK;
+}
+
+// RES = PHI - D_bb X for every field (FP64) and its norms.
+int batch_true_residual(dwa_ctx* ctx, int nr, hipStream_t st, double* res2) {
+  BatchWs& w = ctx->batch;
+  const size_t n = field_elems(ctx);
+  DWA_TRY(apply_dbb(ctx, DWA_F64, w.f64[B_Q], w.f64[B_X], w.f64[B_OPB], w.f64[B_OPR], nr));
+  DWA_TRY(launch_axpby(ctx, DWA_F64, w.f64[B_RES], 1.0, w.f64[B_PHI], 0.0, n, nr));
+  DWA_TRY(launch_axpby(ctx, DWA_F64, w.f64[B_RES], -1.0, w.f64[B_Q], 1.0, n, nr));
+  return batch_norms(ctx, DWA_F64, w.f64[B_RES], nr, st, res2);
+}
+
 }  // namespace
 
 extern "C" {
@@ -665,6 +902,7 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
 
 int dwa_destroy(dwa_ctx* ctx) {
   if (!ctx) return DWA_OK;
+  free_batch(ctx);
   auto f = [](void* p) {
     if (p) (void)hipFree(p);
   };
@@ -771,6 +1009,33 @@ int dwa_apply_Dbb(dwa_ctx* ctx, int prec, void* out, const void* in) {
   void** W = low_pool(ctx, prec);
   const bool p64 = prec == DWA_F64;
   return apply_dbb(ctx, prec, out, in, W[p64 ? W_OPB : L_OPB], W[p64 ? W_OPR : L_OPR]);
+}
+
+int dwa_apply_Dbb_batch(dwa_ctx* ctx, int prec, int nrhs, void* out, const void* in,
+                        double* out_norm2) {
+  DWA_TRY(check_ctx(ctx));
+  if (!out || !in) return einval("null field");
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (out == in) return einval("out and in must not overlap");
+  if (nrhs < 1 || nrhs > ctx->batch.nmax) return einval("batch larger than reserved (dwa_reserve_batch)");
+  BatchWs& w = ctx->batch;
+  void* tb = prec == DWA_F64 ? w.f64[B_OPB] : w.lo[prec][BL_U];
+  void* tr = prec == DWA_F64 ? w.f64[B_OPR] : w.lo[prec][BL_T];
+  if (!out_norm2) return apply_dbb(ctx, prec, out, in, tb, tr, nrhs);
+  // with the per-field |out|^2 from the partial sums of the second hop
+  int nb = 0;
+  DWA_TRY(launch_smix(ctx, prec, MIX_BG, tb, in, nullptr, 0.0, ctx->Ls, nullptr, nullptr, nrhs));
+  DWA_TRY(dbb_from_premix(ctx, prec, out, in, tb, tr, bbank(ctx, 0), &nb, nrhs));
+  std::vector<double> h(size_t(nb) * nrhs);
+  DWA_HIP(hipMemcpyAsync(h.data(), bbank(ctx, 0), sizeof(double) * h.size(), hipMemcpyDeviceToHost, ctx->stream),
+          "norm readback");
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "norm sync");
+  for (int f = 0; f < nrhs; ++f) {
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) acc += h[size_t(f) * nb + i];
+    out_norm2[f] = acc;
+  }
+  return DWA_OK;
 }
 
 int dwa_apply_Dbb_dag(dwa_ctx* ctx, int prec, void* out, const void* in) {
@@ -1069,6 +1334,257 @@ int dwa_propagator_adjoint(dwa_ctx* ctx, void* gU, void* geta, double* galpha, d
   }
   if (status == DWA_ENOCONV) set_error("forward or adjoint solve reached maxiter");
   return status;
+}
+
+int dwa_reserve_batch(dwa_ctx* ctx, int nmax) {
+  if (!ctx) return einval("null context");
+  if (nmax < 1 || nmax > 4096) return einval("batch size must be in [1, 4096]");
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "reserve sync");
+  free_batch(ctx);
+  BatchWs& b = ctx->batch;
+  const size_t n = field_elems(ctx);
+  auto fail = [&](int rc) {
+    free_batch(ctx);
+    return rc;
+  };
+  int rc = DWA_OK;
+  for (int i = 0; i < B_COUNT; ++i)
+    if ((rc = hip_fail(hipMalloc(&b.f64[i], 16 * n * nmax), "alloc batch fp64"))) return fail(rc);
+  for (int pr : {DWA_F32, DWA_BF16})
+    for (int i = 0; i < BL_COUNT; ++i)
+      if ((rc = hip_fail(hipMalloc(&b.lo[pr][i], elem_bytes(pr) * n * nmax), "alloc batch low")))
+        return fail(rc);
+  if ((rc = hip_fail(hipMalloc(&b.xacc, 8 * n * nmax), "alloc batch acc"))) return fail(rc);
+  if ((rc = hip_fail(hipMalloc(&b.d_scal, sizeof(DevScalars) * nmax), "alloc batch scalars"))) return fail(rc);
+  if ((rc = hip_fail(hipMemset(b.d_scal, 0, sizeof(DevScalars) * nmax), "clear batch scalars"))) return fail(rc);
+  b.bank_elems = size_t(ctx->Vh) + 8192;
+  if ((rc = hip_fail(hipMalloc(&b.partials, sizeof(double) * 4 * nmax * b.bank_elems), "alloc batch partials")))
+    return fail(rc);
+  if ((rc = hip_fail(hipMalloc(&b.d_coef, sizeof(double) * 4 * nmax), "alloc batch coefficients"))) return fail(rc);
+  if ((rc = hip_fail(hipHostMalloc(&b.h_scal, sizeof(DevScalars) * nmax, hipHostMallocDefault), "alloc pinned")))
+    return fail(rc);
+  if ((rc = hip_fail(hipHostMalloc(&b.h_coef, sizeof(double) * 4 * nmax, hipHostMallocDefault), "alloc pinned")))
+    return fail(rc);
+  if ((rc = hip_fail(hipHostMalloc(&b.h_active, sizeof(int) * nmax, hipHostMallocDefault), "alloc pinned")))
+    return fail(rc);
+  if ((rc = hip_fail(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking), "batch stream")))
+    return fail(rc);
+  b.nmax = nmax;
+  return DWA_OK;
+}
+
+int dwa_propagator_multi(dwa_ctx* const* ctxs, int nctx, const int* nrhs, void* const* y1,
+                         const void* const* eta, const dwa_solve_opts* o, dwa_solve_stats* stats) {
+  if (!ctxs || nctx < 1 || !nrhs || !y1 || !eta || !o) return einval("null argument or nctx < 1");
+  if (!(o->tol > 0.0) || o->maxiter < 0) return einval("bad tolerance or maxiter");
+  if (!valid_prec(o->inner_prec)) return einval("bad inner precision");
+  for (int i = 0; i < nctx; ++i) {
+    DWA_TRY(check_ctx(ctxs[i]));
+    if (nrhs[i] < 1 || nrhs[i] > ctxs[i]->batch.nmax)
+      return einval("batch larger than reserved (dwa_reserve_batch)");
+    if (!y1[i] || !eta[i]) return einval("null field");
+    if (ctxs[i]->device != ctxs[0]->device) return einval("contexts on different devices");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return einval("a context appears twice");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = ctxs[0]->batch.stream;
+  std::vector<hipStream_t> saved(nctx);
+  for (int i = 0; i < nctx; ++i) {
+    DWA_HIP(hipStreamSynchronize(ctxs[i]->stream), "multi entry sync");
+    saved[i] = ctxs[i]->stream;
+    ctxs[i]->stream = st;
+  }
+  auto restore = [&]() {
+    for (int i = 0; i < nctx; ++i) ctxs[i]->stream = saved[i];
+  };
+  auto run = [&]() -> int {
+    // source and Schur right-hand side of every field
+    for (int i = 0; i < nctx; ++i) {
+      dwa_ctx* ctx = ctxs[i];
+      BatchWs& w = ctx->batch;
+      const int nr = nrhs[i], Ls = ctx->Ls;
+      const size_t n = field_elems(ctx), v12 = size_t(ctx->V) * 12;
+      auto at = [&](int role, int f) { return static_cast<void*>(static_cast<double2*>(w.f64[role]) + f * n); };
+      for (int f = 0; f < nr; ++f)
+        DWA_TRY(launch_source(ctx, at(B_CHI_B, f), at(B_CHI_R, f), at(B_RHO_B, f), at(B_RHO_R, f),
+                              static_cast<const double2*>(eta[i]) + f * v12));
+      HopOp hb{w.f64[B_CHI_R], w.f64[B_RHO_B], w.f64[B_RHO_B], nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 0, Ls, nullptr, nr};
+      HopOp hr{w.f64[B_CHI_B], w.f64[B_RHO_R], w.f64[B_RHO_R], nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 1, Ls, nullptr, nr};
+      DWA_TRY(launch_hop(ctx, DWA_F64, hb, nullptr));
+      DWA_TRY(launch_hop(ctx, DWA_F64, hr, nullptr));
+      DWA_TRY(launch_smix(ctx, DWA_F64, MIX_N, w.f64[B_T], w.f64[B_RHO_R], nullptr, 0.0, Ls, nullptr, nullptr, nr));
+      HopOp prep{w.f64[B_T], w.f64[B_PHI], w.f64[B_RHO_B], nullptr, 0.5, 1.0, 0.0, MIX_GINV_IINV, 0, Ls, nullptr, nr};
+      DWA_TRY(launch_hop(ctx, DWA_F64, prep, nullptr));
+    }
+    // solve D_bb X = PHI for every field
+    const int inner = o->inner_prec;
+    std::vector<std::vector<double>> rel(nctx), bnorm(nctx);
+    std::vector<std::vector<int>> iters(nctx), outer(nctx), fp64_conv(nctx);
+    for (int i = 0; i < nctx; ++i) {
+      rel[i].assign(nrhs[i], 1.0);
+      bnorm[i].assign(nrhs[i], 0.0);
+      iters[i].assign(nrhs[i], 0);
+      outer[i].assign(nrhs[i], 0);
+      DWA_TRY(batch_norms(ctxs[i], DWA_F64, ctxs[i]->batch.f64[B_PHI], nrhs[i], st, bnorm[i].data()));
+      for (auto& v : bnorm[i]) v = std::sqrt(v);
+    }
+    if (inner == DWA_F64) {
+      std::vector<BatchSys> S(nctx);
+      for (int i = 0; i < nctx; ++i) {
+        S[i].ctx = ctxs[i];
+        S[i].nr = nrhs[i];
+        S[i].prec = DWA_F64;
+        S[i].x = ctxs[i]->batch.f64[B_X];
+        S[i].rhs = ctxs[i]->batch.f64[B_PHI];
+        S[i].tol.assign(nrhs[i], o->tol);
+        batch_sys_vectors(S[i]);
+      }
+      DWA_TRY(cgls_multi(S, st, o->maxiter, o->check_every, true));
+      for (int i = 0; i < nctx; ++i) {
+        iters[i] = S[i].iters;
+        fp64_conv[i] = S[i].converged;
+      }
+    } else {
+      // defect correction: FP64 residuals, one batched low-precision CGLS per round
+      const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
+      std::vector<std::vector<int>> stall(nctx);
+      std::vector<std::vector<double>> prev(nctx);
+      for (int i = 0; i < nctx; ++i) {
+        BatchWs& w = ctxs[i]->batch;
+        const size_t n = field_elems(ctxs[i]);
+        DWA_TRY(launch_zero(ctxs[i], DWA_F64, w.f64[B_X], n, nrhs[i]));
+        DWA_TRY(launch_axpby(ctxs[i], DWA_F64, w.f64[B_RES], 1.0, w.f64[B_PHI], 0.0, n, nrhs[i]));
+        stall[i].assign(nrhs[i], 0);
+        prev[i].assign(nrhs[i], 1.0);
+        for (int f = 0; f < nrhs[i]; ++f)
+          if (bnorm[i][f] == 0.0) rel[i][f] = 0.0;
+      }
+      int total = 0;
+      for (;;) {
+        // one batched low-precision CGLS over the contexts that still have live fields
+        std::vector<BatchSys> S;
+        std::vector<int> which;
+        for (int i = 0; i < nctx; ++i) {
+          dwa_ctx* ctx = ctxs[i];
+          BatchWs& w = ctx->batch;
+          const int nr = nrhs[i];
+          const size_t n = field_elems(ctx);
+          BatchSys b;
+          b.ctx = ctx;
+          b.nr = nr;
+          b.prec = inner;
+          b.x = w.xacc;
+          b.rhs = w.lo[inner][BL_RHS];
+          b.tol.assign(nr, -1.0);
+          batch_sys_vectors(b);
+          bool live_any = false;
+          for (int f = 0; f < nr; ++f) {
+            const bool live = rel[i][f] > o->tol && stall[i][f] < 3;
+            w.h_coef[f] = live ? 1.0 / (rel[i][f] * bnorm[i][f]) : 0.0;
+            if (live) {
+              b.tol[f] = std::max(delta, 0.5 * o->tol / rel[i][f]);
+              live_any = true;
+            }
+          }
+          if (!live_any) continue;
+          // right-hand sides r / |r| in the inner storage precision
+          DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
+          DWA_TRY(launch_convert(ctx, inner, w.lo[inner][BL_RHS], DWA_F64, w.f64[B_RES], n, 0.0, nr, w.d_coef));
+          S.push_back(std::move(b));
+          which.push_back(i);
+        }
+        if (S.empty() || total >= o->maxiter) break;
+        DWA_TRY(cgls_multi(S, st, o->maxiter - total, o->check_every, true));
+        int round_max = 0;
+        for (size_t j = 0; j < S.size(); ++j) {
+          const int i = which[j];
+          dwa_ctx* ctx = ctxs[i];
+          BatchWs& w = ctx->batch;
+          const int nr = nrhs[i];
+          const size_t n = field_elems(ctx);
+          for (int f = 0; f < nr; ++f) {
+            const bool live = S[j].tol[f] >= 0.0;
+            w.h_coef[f] = live ? rel[i][f] * bnorm[i][f] : 0.0;
+            if (live) {
+              iters[i][f] += S[j].iters[f];
+              outer[i][f] += 1;
+              round_max = std::max(round_max, S[j].iters[f]);
+            }
+          }
+          // X += |r| e in FP64, then the new residuals
+          DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
+          DWA_TRY(launch_convert(ctx, DWA_F64, w.f64[B_OPB], xacc_prec(inner), w.xacc, n, 0.0, nr, w.d_coef));
+          DWA_TRY(launch_axpby(ctx, DWA_F64, w.f64[B_X], 1.0, w.f64[B_OPB], 1.0, n, nr));
+          std::vector<double> r2(nr);
+          DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));
+          for (int f = 0; f < nr; ++f) {
+            if (S[j].tol[f] < 0.0) continue;
+            const double r = bnorm[i][f] > 0.0 ? std::sqrt(r2[f]) / bnorm[i][f] : 0.0;
+            if (!(r < 0.9 * prev[i][f])) stall[i][f] += 1;
+            else stall[i][f] = 0;
+            prev[i][f] = r;
+            rel[i][f] = r;
+          }
+        }
+        total += std::max(round_max, 1);
+      }
+    }
+    // final residuals, reconstruction and extraction
+    int status = DWA_OK;
+    size_t off = 0;
+    for (int i = 0; i < nctx; ++i) {
+      dwa_ctx* ctx = ctxs[i];
+      BatchWs& w = ctx->batch;
+      const int nr = nrhs[i], Ls = ctx->Ls;
+      const size_t n = field_elems(ctx), v12 = size_t(ctx->V) * 12;
+      std::vector<double> r2(nr);
+      DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));
+      DWA_TRY(launch_smix(ctx, DWA_F64, MIX_BG, w.f64[B_OPB], w.f64[B_X], nullptr, 0.0, Ls, nullptr, nullptr, nr));
+      HopOp rec{w.f64[B_OPB], w.f64[B_PSI_R], w.f64[B_RHO_R], nullptr, 0.5, 1.0, 0.0, MIX_GINV_IINV, 1, Ls, nullptr, nr};
+      DWA_TRY(launch_hop(ctx, DWA_F64, rec, nullptr));
+      for (int f = 0; f < nr; ++f)
+        DWA_TRY(launch_extract(ctx, static_cast<double2*>(y1[i]) + f * v12,
+                               static_cast<const double2*>(w.f64[B_X]) + f * n,
+                               static_cast<const double2*>(w.f64[B_PSI_R]) + f * n));
+      for (int f = 0; f < nr; ++f) {
+        const double r = bnorm[i][f] > 0.0 ? std::sqrt(r2[f]) / bnorm[i][f] : 0.0;
+        // FP64: the CGLS stopping rule (recursive residual), as dwa_cgne_solve; mixed
+        // precision: the FP64 residual that ends the defect correction
+        const bool conv = inner == DWA_F64 ? fp64_conv[i][f] != 0 : r <= o->tol;
+        if (!conv) status = DWA_ENOCONV;
+        if (stats) {
+          dwa_solve_stats& sf = stats[off + f];
+          sf = dwa_solve_stats{};
+          sf.iters = iters[i][f];
+          sf.outer = outer[i][f];
+          sf.converged = conv;
+          sf.rel_resid = r;
+        }
+      }
+      off += nr;
+    }
+    DWA_HIP(hipStreamSynchronize(st), "multi sync");
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats)
+      for (size_t k = 0; k < off; ++k) stats[k].time_ms = ms;
+    return status;
+  };
+  const int status = run();
+  if (status != DWA_OK && status != DWA_ENOCONV) (void)hipStreamSynchronize(st);
+  restore();
+  if (status == DWA_ENOCONV) set_error("some field of the batch did not converge");
+  return status;
+}
+
+int dwa_propagator_batch(dwa_ctx* ctx, int nrhs, void* y1, const void* eta, const dwa_solve_opts* o,
+                         dwa_solve_stats* stats) {
+  dwa_ctx* const c[1] = {ctx};
+  const int n[1] = {nrhs};
+  void* const y[1] = {y1};
+  const void* const e[1] = {eta};
+  if (!ctx) return einval("null context");
+  return dwa_propagator_multi(c, 1, n, y, e, o, stats);
 }
 
 // Host-only access to the site-local matrices (no device needed); used to check

@@ -194,7 +194,8 @@ struct DevScalars {
   double b2;      // |rhs|^2
   double aux;     // spare
   int flags;      // bit 0: |q|^2 not positive/finite; bit 1: |z|^2 not finite
-  int pad[3];
+  int active;     // 0: the field is frozen (converged or stopped), set by the host
+  int pad[2];
 };
 
 struct PrecFields {  // one precision's copy of the links
@@ -211,6 +212,32 @@ enum W64Role {
 // low-precision (F32 or BF16 storage) workspace roles
 enum LowRole { L_R = 0, L_P, L_Z, L_Q, L_W, L_U, L_T /* red */, L_X, L_OPB, L_OPR /* red */, LOW_COUNT };
 
+}  // namespace dwa
+
+namespace dwa {
+// FP64 roles of a batch of fields (dwa_reserve_batch): solution, right-hand side, CGLS
+// vectors, residual and temporaries, and the propagator's source and prep fields
+enum BatchRole {
+  B_X = 0, B_PHI, B_R, B_P, B_Z, B_Q, B_W, B_U, B_T /* red */, B_RES, B_OPB, B_OPR /* red */,
+  B_RHO_B, B_RHO_R, B_CHI_B, B_CHI_R, B_PSI_R, B_COUNT
+};
+// low-precision roles of a batch: CGLS vectors of the inner solve, its right-hand side
+// and (FP32, also for BF16 fields) its accumulated solution
+enum BatchLowRole { BL_R = 0, BL_P, BL_Z, BL_Q, BL_W, BL_U, BL_T /* red */, BL_RHS, BL_COUNT };
+struct BatchWs {
+  int nmax = 0;                   // fields reserved
+  void* f64[B_COUNT] = {};        // nmax fields each
+  void* lo[3][BL_COUNT] = {};     // per storage precision (index = dwa_prec; [0] unused)
+  void* xacc = nullptr;           // FP32 accumulated low-precision solution, nmax fields
+  DevScalars* d_scal = nullptr;   // nmax
+  DevScalars* h_scal = nullptr;   // pinned mirror
+  double* partials = nullptr;     // 4 banks of nmax * bank_elems
+  size_t bank_elems = 0;          // per field
+  double* d_coef = nullptr;       // per-field coefficient tables (4 * nmax)
+  double* h_coef = nullptr;       // pinned staging for d_coef
+  int* h_active = nullptr;        // pinned staging for the active flags
+  hipStream_t stream = nullptr;   // capture stream of batched solves
+};
 }  // namespace dwa
 
 struct dwa_ctx {
@@ -250,12 +277,11 @@ struct dwa_ctx {
   dwa::DevScalars* d_scal = nullptr;
   dwa::DevScalars* h_scal = nullptr;  // pinned
   double* d_red = nullptr;          // small result slots for standalone reductions
+  dwa::BatchWs batch;               // dwa_reserve_batch
 };
 
 namespace dwa {
 
-// Sites per block of the fused hop kernel: 16 for the Ls with their own kernels
-// (4, 8, 12, 16), 8 for the generic kernel (Ls <= 32).
 // Sites per block of the fused hop: Ls values with their own kernels run 32 sites
 // (FP32 / BF16: one 128-byte line per colour-spin component and slice) or 16 (FP64,
 // whose LDS tile is twice as large); the generic and dense kernels run 8.
@@ -276,22 +302,28 @@ struct HopOp {
   int mix;              // MixKind applied to h' (MIX_IDENTITY = none)
   int parity_out;
   int nslices;          // number of 5D slices (Ls, or n for plain D_w)
-  double* partials;     // optional per-block |out|^2 partial sums
+  double* partials;     // optional per-block |out|^2 partial sums (grouped per field)
+  int nrhs = 1;         // batch of fields, field_elems apart (partials: nblocks per field)
 };
 
 int launch_hop(dwa_ctx* ctx, int prec, const HopOp& op, int* nblocks_out);
+// Batched forms: nrhs fields field_elems(ctx) apart; per-field partial sums are packed
+// (field r at partials[r * nblocks ...]) and per-field coefficient tables are device
+// arrays (axpby: (a, b) pairs; convert: scales).
 int launch_smix(dwa_ctx* ctx, int prec, int mix, void* out, const void* in, const void* post,
-                double post_coef, int nslices, double* partials, int* nblocks_out);
+                double post_coef, int nslices, double* partials, int* nblocks_out, int nrhs = 1);
 int launch_pack_links(dwa_ctx* ctx, int prec, void* dst, const void* src_canon);
 int launch_pack5(dwa_ctx* ctx, int prec, void* dst_soa, const void* src_canon, int parity,
                  int nslices);
 int launch_unpack5(dwa_ctx* ctx, int prec, void* dst_canon, const void* src_soa, int parity,
                    int nslices);
 int launch_convert(dwa_ctx* ctx, int prec_out, void* out, int prec_in, const void* in, size_t n,
-                   double scale);
-int launch_zero(dwa_ctx* ctx, int prec, void* p, size_t n);
-int launch_axpby(dwa_ctx* ctx, int prec, void* y, double a, const void* x, double b, size_t n);
-int launch_norm2(dwa_ctx* ctx, int prec, const void* x, size_t n, double* partials, int* nblocks);
+                   double scale, int nrhs = 1, const double* scales = nullptr);
+int launch_zero(dwa_ctx* ctx, int prec, void* p, size_t n, int nrhs = 1);
+int launch_axpby(dwa_ctx* ctx, int prec, void* y, double a, const void* x, double b, size_t n,
+                 int nrhs = 1, const double* ab = nullptr);
+int launch_norm2(dwa_ctx* ctx, int prec, const void* x, size_t n, double* partials, int* nblocks,
+                 int nrhs = 1);
 int launch_sum_partials(dwa_ctx* ctx, const double* partials, int n, double* out);
 int launch_source(dwa_ctx* ctx, void* chi_b, void* chi_r, void* aux_b, void* aux_r, const void* eta);
 int launch_extract(dwa_ctx* ctx, void* y1, const void* psi_b, const void* psi_r);
@@ -302,11 +334,12 @@ int launch_check_finite(dwa_ctx* ctx, const void* canon, size_t ncomplex, int* d
 // adj = true runs the updates of CGLS on D_bb^dag (premixes swapped; FP64 only).
 int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
                       const void* q, const DevScalars* s, double* partials, int* nblocks,
-                      bool adj = false);
+                      bool adj = false, int nrhs = 1);
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
-                      const DevScalars* s, bool adj = false);
+                      const DevScalars* s, bool adj = false, int nrhs = 1);
+// one block per field: s[r] from partials_a[r * na ...] and partials_b[r * nb ...]
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* partials_a, int na,
-                       const double* partials_b, int nb);
+                       const double* partials_b, int nb, int nrhs = 1);
 int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f);
 
 // gradient path (adjoint.hip), FP64 SoA fields; "lt" is g5 lambda
@@ -324,18 +357,20 @@ int launch_geta(dwa_ctx* ctx, void* geta, const void* lt_b, const void* lt_r, co
 // per-precision launchers (kcommon.h), instantiated in kernels_{f64,f32,bf16}.hip
 template <typename S> int launch_hop_p(dwa_ctx*, const HopOp&, int*);
 template <typename S> int launch_smix_p(dwa_ctx*, int, void*, const void*, const void*, double, int,
-                                        double*, int*);
+                                        double*, int*, int);
 template <typename S> int launch_update1_p(dwa_ctx*, void*, void*, void*, const void*, const void*,
-                                           const DevScalars*, double*, int*, bool);
+                                           const DevScalars*, double*, int*, bool, int);
 template <typename S> int launch_update2_p(dwa_ctx*, void*, void*, const void*, const DevScalars*,
-                                           bool);
-template <typename S> int norm2_p(dwa_ctx*, const void*, size_t, double*, int*);
-template <typename S> int axpby_p(dwa_ctx*, void*, double, const void*, double, size_t);
-template <typename S> int zero_p(dwa_ctx*, void*, size_t);
+                                           bool, int);
+template <typename S> int norm2_p(dwa_ctx*, const void*, size_t, double*, int*, int);
+template <typename S> int axpby_p(dwa_ctx*, void*, double, const void*, double, size_t, int,
+                                  const double*);
+template <typename S> int zero_p(dwa_ctx*, void*, size_t, int);
 template <typename S> int pack5_p(dwa_ctx*, void*, const void*, int, int);
 template <typename S> int unpack5_p(dwa_ctx*, void*, const void*, int, int);
 template <typename S> int pack_links_p(dwa_ctx*, void*, const void*);
-template <typename SO, typename SI> int convert_p(dwa_ctx*, void*, const void*, size_t, double);
+template <typename SO, typename SI> int convert_p(dwa_ctx*, void*, const void*, size_t, double, int,
+                                                  const double*);
 
 size_t field_elems(const dwa_ctx* ctx);  // Ls * 12 * Vh complex numbers
 void set_error(const std::string& msg);

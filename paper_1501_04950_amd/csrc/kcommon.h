@@ -65,8 +65,13 @@ template <typename S>
 __device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
                                       cpx<typename S::real> v) {
   if constexpr (S::prec == DWA_F64) {
+    // A store of more than 64 bits must not have its data registers rewritten by the
+    // very next VALU instruction.  The compiler inserts that wait state only when the
+    // store has no register scalar offset, yet gfx950 needs it either way (with an SGPR
+    // soffset the imaginary half of the last store of a loop was seen overwritten by
+    // the norm that followed it).  So the whole offset goes into the lane offset.
     const dwa_v2d d = {v.re, v.im};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(dwa_v4u, d), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(dwa_v4u, d), r, voff + soff, 0, 0);
   } else if constexpr (S::prec == DWA_F32) {
     const dwa_v2f f = {v.re, v.im};
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(dwa_v2u, f), r, voff, soff, 0);
@@ -405,13 +410,29 @@ struct HopDev {
   int parity_out;
   int nslices;
   unsigned Vh;
+  unsigned nrhs;                 // fields in a batch (1 for a single field)
+  unsigned long long rhs_stride; // elements from one field of the batch to the next
 };
+
+// The fields of batch entry rhs (pointers moved by rhs * rhs_stride elements).
+template <typename S>
+__device__ __forceinline__ HopDev hop_for_rhs(const HopDev& a0, unsigned rhs) {
+  using E = typename S::elem;
+  HopDev a = a0;
+  const size_t roff = size_t(rhs) * a0.rhs_stride;
+  a.in = (const E*)a0.in + roff;
+  a.out = (E*)a0.out + roff;
+  if (a0.pre) a.pre = (const E*)a0.pre + roff;
+  if (a0.post) a.post = (const E*)a0.post + roff;
+  return a;
+}
 
 // Hop without a fifth-dimension mix: one thread per (site, slice).
 template <typename S>
-__global__ void __launch_bounds__(128) hop_plain_kernel(HopDev a) {
+__global__ void __launch_bounds__(128) hop_plain_kernel(HopDev a0) {
   using R = RealOf<S>;
   using E = typename S::elem;
+  const HopDev a = hop_for_rhs<S>(a0, blockIdx.z);
   const unsigned site = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned s = blockIdx.y;
   double nrm = 0.0;
@@ -429,7 +450,8 @@ __global__ void __launch_bounds__(128) hop_plain_kernel(HopDev a) {
       nrm += (double)norm2(o);
     }
   }
-  if (a.partials) block_sum_to(nrm, &a.partials[blockIdx.y * gridDim.x + blockIdx.x]);
+  if (a.partials)
+    block_sum_to(nrm, &a.partials[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x]);
 }
 
 // Blocks are dealt to the 8 XCDs round robin; remap so that each XCD works on one
@@ -586,9 +608,15 @@ __device__ __forceinline__ double hop_mix_out(const HopDev& a, const lcpx<RealOf
 //      only epilogue that also writes per-block partial sums of |out|^2)
 //   2: out = M (hop_coef H in + pre_coef pre)     (Schur prep and reconstruction)
 template <typename S, int NS, int LS, int MODE, int KIND, bool DENSE>
-__global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a) {
+__global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a0) {
   using R = RealOf<S>;
   using E = typename S::elem;
+  // field rhs of a batch = blockIdx.y; chunk of sites from the XCD-aware block order.
+  // (No integer division by a runtime value here: its float-reciprocal expansion,
+  // rematerialised after the divergent phases, mis-indexed the partial sums.)
+  const unsigned rhs = blockIdx.y;
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const HopDev a = hop_for_rhs<S>(a0, rhs);
   constexpr int LSM = LS > 0 ? LS : 32;
   constexpr int NSP = NS + 1;
   extern __shared__ __align__(16) char smem_raw[];
@@ -599,7 +627,6 @@ __global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a
                             ? size_t(Ls) * 12 * NSP * sizeof(cpx<R>)
                             : size_t(72) * NS * sizeof(cpx<R>);
   unsigned* lnbr = reinterpret_cast<unsigned*>(smem_raw + region);
-  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const unsigned site0 = (a.blkmap ? (unsigned)a.blkmap[blk] : blk) * NS;
   const int p = a.parity_out;
   const unsigned Vh = a.Vh;
@@ -671,7 +698,7 @@ __global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a
     else
       nrm += hop_mix_out<S, NS, LSM, MODE, KIND, 1, DENSE>(a, tile, site0, Ls, lt);
   }
-  if (MODE == 1 && a.partials) block_sum_to(nrm, &a.partials[blockIdx.x]);
+  if (MODE == 1 && a.partials) block_sum_to(nrm, &a.partials[rhs * gridDim.x + blk]);
 }
 
 // Site-local kernels run one thread per (site, colour-spin component of one chirality)
@@ -692,6 +719,12 @@ __global__ void __launch_bounds__(256) smix_kernel(typename S::elem* __restrict_
   constexpr int LSM = LS > 0 ? LS : 32;
   const int Ls = LS > 0 ? LS : Ls_rt;
   DWA_SITE_THREAD;
+  {  // batch entry blockIdx.y
+    const size_t roff = size_t(blockIdx.y) * (size_t(Ls) * 12 * Vh);
+    out += roff;
+    in += roff;
+    if (post) post += roff;
+  }
   double nrm = 0.0;
   if (live) {
 #pragma unroll
@@ -714,7 +747,7 @@ __global__ void __launch_bounds__(256) smix_kernel(typename S::elem* __restrict_
         }
     }
   }
-  if (partials) block_sum_to(nrm, &partials[blockIdx.x]);
+  if (partials) block_sum_to(nrm, &partials[blockIdx.y * gridDim.x + blockIdx.x]);
 }
 
 // CGLS update 1: x += a p ; r -= a q ; |r|^2 ; w = (g5 I^-T G^-1) r
@@ -731,6 +764,15 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type:
   constexpr int LSM = LS > 0 ? LS : 32;
   const int Ls = LS > 0 ? LS : Ls_rt;
   DWA_SITE_THREAD;
+  {  // batch entry blockIdx.y
+    const size_t roff = size_t(blockIdx.y) * (size_t(Ls) * 12 * Vh);
+    x += roff;
+    r += roff;
+    w += roff;
+    p += roff;
+    q += roff;
+    sc += blockIdx.y;
+  }
   double nrm = 0.0;
   if (live) {
     const R a = (R)sc->a;
@@ -758,7 +800,7 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type:
         if (i < Ls) st<S>(w, (size_t(i) * 12 + comp) * Vh + site, rv[i]);
     }
   }
-  if (partials) block_sum_to(nrm, &partials[blockIdx.x]);
+  if (partials) block_sum_to(nrm, &partials[blockIdx.y * gridDim.x + blockIdx.x]);
 }
 
 // CGLS update 2: p = z + beta p ; u = (B G) p
@@ -772,6 +814,13 @@ __global__ void __launch_bounds__(256) cg_update2_kernel(typename S::elem* __res
   constexpr int LSM = LS > 0 ? LS : 32;
   const int Ls = LS > 0 ? LS : Ls_rt;
   DWA_SITE_THREAD;
+  {  // batch entry blockIdx.y
+    const size_t roff = size_t(blockIdx.y) * (size_t(Ls) * 12 * Vh);
+    p += roff;
+    u += roff;
+    z += roff;
+    sc += blockIdx.y;
+  }
   if (!live) return;
   const R beta = (R)sc->beta;
 #pragma unroll
@@ -797,18 +846,26 @@ __global__ void __launch_bounds__(256) cg_update2_kernel(typename S::elem* __res
 template <typename S>
 __global__ void __launch_bounds__(256) norm2_kernel(const typename S::elem* __restrict__ x, size_t n,
                                                     double* partials) {
+  x += size_t(blockIdx.y) * n;  // batch entry
   double v = 0.0;
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
        i += size_t(gridDim.x) * blockDim.x)
     v += (double)norm2(ld<S>(x, i));
-  block_sum_to(v, &partials[blockIdx.x]);
+  block_sum_to(v, &partials[blockIdx.y * gridDim.x + blockIdx.x]);
 }
 
 template <typename S>
 __global__ void __launch_bounds__(256) axpby_kernel(typename S::elem* __restrict__ y, double a,
                                                     const typename S::elem* __restrict__ x, double b,
-                                                    size_t n) {
+                                                    size_t n, const double* __restrict__ ab) {
   using R = RealOf<S>;
+  // batch entry blockIdx.y, with its own (a, b) when a table is given
+  y += size_t(blockIdx.y) * n;
+  x += size_t(blockIdx.y) * n;
+  if (ab) {
+    a = ab[2 * blockIdx.y];
+    b = ab[2 * blockIdx.y + 1];
+  }
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
        i += size_t(gridDim.x) * blockDim.x) {
     cpx<R> o = (R)a * ld<S>(x, i);
@@ -820,7 +877,12 @@ __global__ void __launch_bounds__(256) axpby_kernel(typename S::elem* __restrict
 template <typename SO, typename SI>
 __global__ void __launch_bounds__(256) convert_kernel(typename SO::elem* __restrict__ out,
                                                       const typename SI::elem* __restrict__ in,
-                                                      size_t n, double scale) {
+                                                      size_t n, double scale,
+                                                      const double* __restrict__ scales) {
+  // batch entry blockIdx.y, with its own scale when a table is given
+  out += size_t(blockIdx.y) * n;
+  in += size_t(blockIdx.y) * n;
+  if (scales) scale = scales[blockIdx.y];
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
        i += size_t(gridDim.x) * blockDim.x) {
     cpx<RealOf<SI>> v = ld<SI>(in, i);
@@ -834,6 +896,7 @@ __global__ void __launch_bounds__(256) convert_kernel(typename SO::elem* __restr
 template <typename S>
 __global__ void __launch_bounds__(256) zero_kernel(typename S::elem* __restrict__ p, size_t n) {
   using R = RealOf<S>;
+  p += size_t(blockIdx.y) * n;  // batch entry
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
        i += size_t(gridDim.x) * blockDim.x)
     st<S>(p, i, cmk<R>(0, 0));
@@ -947,11 +1010,11 @@ MixTables mix_tables(dwa_ctx* ctx, int kind) {
   }
 
 template <typename S, int MODE, int KIND>
-void launch_hop_mix_mk(dwa_ctx* ctx, const HopDev& a, unsigned grid, dim3 block, size_t shm) {
+void launch_hop_mix_mk(dwa_ctx* ctx, const HopDev& a, dim3 grid, dim3 block, size_t shm) {
 #define DWA_HOPMIX(LSV, DV)                                                                   \
   {                                                                                           \
     constexpr int NSV = LSV > 0 ? (S::prec == DWA_F64 ? 16 : 32) : 8;                         \
-    hipLaunchKernelGGL((hop_mix_kernel<S, NSV, LSV, MODE, KIND, DV>), dim3(grid), block, shm, \
+    hipLaunchKernelGGL((hop_mix_kernel<S, NSV, LSV, MODE, KIND, DV>), grid, block, shm,       \
                        ctx->stream, a);                                                       \
   }
   DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_HOPMIX)
@@ -977,8 +1040,11 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
   a.parity_out = op.parity_out;
   a.nslices = op.nslices;
   a.Vh = (unsigned)ctx->Vh;
+  const unsigned nr = op.nrhs > 0 ? (unsigned)op.nrhs : 1u;
+  a.nrhs = nr;
+  a.rhs_stride = field_elems(ctx);
   if (op.mix == MIX_IDENTITY) {
-    dim3 grid((unsigned)((ctx->Vh + 127) / 128), (unsigned)op.nslices);
+    dim3 grid((unsigned)((ctx->Vh + 127) / 128), (unsigned)op.nslices, nr);
     hipLaunchKernelGGL(hop_plain_kernel<S>, grid, dim3(128), 0, ctx->stream, a);
     if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
     return hip_fail(hipGetLastError(), "hop kernel launch");
@@ -988,7 +1054,8 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
     set_error("fused hop runs on the context's Ls slices");
     return DWA_EINVAL;
   }
-  const unsigned grid = (unsigned)((ctx->Vh + NS - 1) / NS);
+  const unsigned chunks = (unsigned)((ctx->Vh + NS - 1) / NS);
+  const dim3 grid(chunks, nr);
   size_t shm = hop_mix_lds_bytes<RealOf<S>>(NS, Ls);
   if (shm < ctx->hop_min_lds) shm = ctx->hop_min_lds;
   // whole wavefronts: phase 2 hands each wave one chirality, which needs the work
@@ -1020,18 +1087,18 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
     set_error("fused hop: unsupported combination of output matrix and epilogue");
     return DWA_EINVAL;
   }
-  if (nblocks_out) *nblocks_out = (int)grid;
+  if (nblocks_out) *nblocks_out = (int)chunks;  // per field of the batch
   return hip_fail(hipGetLastError(), "hop kernel launch");
 }
 
 template <typename S, int KIND>
 void launch_smix_k(dwa_ctx* ctx, void* out, const void* in, const void* post, double post_coef,
-                   double* partials, int grid) {
+                   double* partials, int grid, int nrhs) {
   using E = typename S::elem;
   const MixTables T = mix_tables<S>(ctx, KIND);
   const unsigned Vh = (unsigned)ctx->Vh;
 #define DWA_SMIX(LSV, DV)                                                                    \
-  hipLaunchKernelGGL((smix_kernel<S, LSV, KIND, DV>), dim3(grid), dim3(256), 0, ctx->stream, \
+  hipLaunchKernelGGL((smix_kernel<S, LSV, KIND, DV>), dim3(grid, nrhs), dim3(256), 0, ctx->stream, \
                      (E*)out, (const E*)in, (const E*)post, post_coef, T, ctx->Ls, Vh, partials)
   DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_SMIX)
 #undef DWA_SMIX
@@ -1039,7 +1106,7 @@ void launch_smix_k(dwa_ctx* ctx, void* out, const void* in, const void* post, do
 
 template <typename S>
 int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* post,
-                  double post_coef, int nslices, double* partials, int* nblocks_out) {
+                  double post_coef, int nslices, double* partials, int* nblocks_out, int nrhs) {
   if (nslices != ctx->Ls) {
     set_error("site-local mix runs on the context's Ls slices");
     return DWA_EINVAL;
@@ -1048,7 +1115,7 @@ int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* 
   if (mix == MIX_I_ALPHA) {  // the site-local block I of D_alpha: dense table, FP64 only
     if constexpr (S::prec == DWA_F64) {
       const MixTables T = mix_tables<S>(ctx, MIX_I_ALPHA);
-      hipLaunchKernelGGL((smix_kernel<S, 0, MIX_I_ALPHA, true>), dim3(grid), dim3(256), 0,
+      hipLaunchKernelGGL((smix_kernel<S, 0, MIX_I_ALPHA, true>), dim3(grid, nrhs), dim3(256), 0,
                          ctx->stream, (double2*)out, (const double2*)in, (const double2*)post,
                          post_coef, T, ctx->Ls, (unsigned)ctx->Vh, partials);
       if (nblocks_out) *nblocks_out = grid;
@@ -1057,10 +1124,10 @@ int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* 
     set_error("site-local I_1 G runs in FP64 only");
     return DWA_EINVAL;
   }
-  if (mix == MIX_BG) launch_smix_k<S, MIX_BG>(ctx, out, in, post, post_coef, partials, grid);
-  else if (mix == MIX_N) launch_smix_k<S, MIX_N>(ctx, out, in, post, post_coef, partials, grid);
+  if (mix == MIX_BG) launch_smix_k<S, MIX_BG>(ctx, out, in, post, post_coef, partials, grid, nrhs);
+  else if (mix == MIX_N) launch_smix_k<S, MIX_N>(ctx, out, in, post, post_coef, partials, grid, nrhs);
   else if (mix == MIX_G5_IINVT_GINV)
-    launch_smix_k<S, MIX_G5_IINVT_GINV>(ctx, out, in, post, post_coef, partials, grid);
+    launch_smix_k<S, MIX_G5_IINVT_GINV>(ctx, out, in, post, post_coef, partials, grid, nrhs);
   else {
     set_error("site-local mix: unsupported matrix kind");
     return DWA_EINVAL;
@@ -1071,7 +1138,7 @@ int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* 
 
 template <typename S>
 int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, const void* q,
-                     const DevScalars* s, double* partials, int* nblocks, bool adj) {
+                     const DevScalars* s, double* partials, int* nblocks, bool adj, int nrhs) {
   using E = typename S::elem;
   using EX = typename XAcc<S>::type::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
@@ -1086,11 +1153,11 @@ int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, con
 #define DWA_U1(LSV, DV)                                                                          \
   if (adj) {                                                                                     \
     if constexpr (S::prec == DWA_F64)                                                            \
-      hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_BG>), dim3(grid), dim3(256), 0,      \
+      hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0, \
                          ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,       \
                          ctx->Ls, Vh, partials);                                                 \
   } else {                                                                                       \
-    hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid), dim3(256), \
+    hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid, nrhs), dim3(256), \
                        0, ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,      \
                        ctx->Ls, Vh, partials);                                                   \
   }
@@ -1101,7 +1168,8 @@ int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, con
 }
 
 template <typename S>
-int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevScalars* s, bool adj) {
+int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevScalars* s, bool adj,
+                     int nrhs) {
   using E = typename S::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
   const int grid = (int)((6u * Vh + 255) / 256);
@@ -1115,10 +1183,10 @@ int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevSca
 #define DWA_U2(LSV, DV)                                                                        \
   if (adj) {                                                                                   \
     if constexpr (S::prec == DWA_F64)                                                          \
-      hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid),       \
+      hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid, nrhs), \
                          dim3(256), 0, ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh); \
   } else {                                                                                     \
-    hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_BG>), dim3(grid), dim3(256), 0,       \
+    hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0, \
                        ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh);              \
   }
   DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_U2)
@@ -1127,22 +1195,23 @@ int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevSca
 }
 
 template <typename S>
-int norm2_p(dwa_ctx* ctx, const void* x, size_t n, double* partials, int* nblocks) {
+int norm2_p(dwa_ctx* ctx, const void* x, size_t n, double* partials, int* nblocks, int nrhs) {
   const int grid = grid_for(n, 256, 2048);
-  hipLaunchKernelGGL(norm2_kernel<S>, dim3(grid), dim3(256), 0, ctx->stream,
+  hipLaunchKernelGGL(norm2_kernel<S>, dim3(grid, nrhs), dim3(256), 0, ctx->stream,
                      (const typename S::elem*)x, n, partials);
   *nblocks = grid;
   return hip_fail(hipGetLastError(), "norm2 launch");
 }
 template <typename S>
-int axpby_p(dwa_ctx* ctx, void* y, double a, const void* x, double b, size_t n) {
-  hipLaunchKernelGGL(axpby_kernel<S>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
-                     (typename S::elem*)y, a, (const typename S::elem*)x, b, n);
+int axpby_p(dwa_ctx* ctx, void* y, double a, const void* x, double b, size_t n, int nrhs,
+            const double* ab) {
+  hipLaunchKernelGGL(axpby_kernel<S>, dim3(grid_for(n, 256), nrhs), dim3(256), 0, ctx->stream,
+                     (typename S::elem*)y, a, (const typename S::elem*)x, b, n, ab);
   return hip_fail(hipGetLastError(), "axpby launch");
 }
 template <typename S>
-int zero_p(dwa_ctx* ctx, void* p, size_t n) {
-  hipLaunchKernelGGL(zero_kernel<S>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
+int zero_p(dwa_ctx* ctx, void* p, size_t n, int nrhs) {
+  hipLaunchKernelGGL(zero_kernel<S>, dim3(grid_for(n, 256), nrhs), dim3(256), 0, ctx->stream,
                      (typename S::elem*)p, n);
   return hip_fail(hipGetLastError(), "zero launch");
 }
@@ -1171,27 +1240,31 @@ int pack_links_p(dwa_ctx* ctx, void* dst, const void* src) {
   return hip_fail(hipGetLastError(), "pack links launch");
 }
 template <typename SO, typename SI>
-int convert_p(dwa_ctx* ctx, void* out, const void* in, size_t n, double scale) {
-  hipLaunchKernelGGL((convert_kernel<SO, SI>), dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
-                     (typename SO::elem*)out, (const typename SI::elem*)in, n, scale);
+int convert_p(dwa_ctx* ctx, void* out, const void* in, size_t n, double scale, int nrhs,
+              const double* scales) {
+  hipLaunchKernelGGL((convert_kernel<SO, SI>), dim3(grid_for(n, 256), nrhs), dim3(256), 0,
+                     ctx->stream, (typename SO::elem*)out, (const typename SI::elem*)in, n, scale,
+                     scales);
   return hip_fail(hipGetLastError(), "convert launch");
 }
 
 #define DWA_INSTANTIATE_PRECISION(S)                                                            \
   template int launch_hop_p<S>(dwa_ctx*, const HopOp&, int*);                                  \
   template int launch_smix_p<S>(dwa_ctx*, int, void*, const void*, const void*, double, int,    \
-                                double*, int*);                                                 \
+                                double*, int*, int);                                            \
   template int launch_update1_p<S>(dwa_ctx*, void*, void*, void*, const void*, const void*,     \
-                                   const DevScalars*, double*, int*, bool);                     \
-  template int launch_update2_p<S>(dwa_ctx*, void*, void*, const void*, const DevScalars*, bool); \
-  template int norm2_p<S>(dwa_ctx*, const void*, size_t, double*, int*);                        \
-  template int axpby_p<S>(dwa_ctx*, void*, double, const void*, double, size_t);                \
-  template int zero_p<S>(dwa_ctx*, void*, size_t);                                              \
+                                   const DevScalars*, double*, int*, bool, int);                \
+  template int launch_update2_p<S>(dwa_ctx*, void*, void*, const void*, const DevScalars*, bool, \
+                                   int);                                                        \
+  template int norm2_p<S>(dwa_ctx*, const void*, size_t, double*, int*, int);                   \
+  template int axpby_p<S>(dwa_ctx*, void*, double, const void*, double, size_t, int,            \
+                          const double*);                                                       \
+  template int zero_p<S>(dwa_ctx*, void*, size_t, int);                                         \
   template int pack5_p<S>(dwa_ctx*, void*, const void*, int, int);                              \
   template int unpack5_p<S>(dwa_ctx*, void*, const void*, int, int);                            \
   template int pack_links_p<S>(dwa_ctx*, void*, const void*);                                   \
-  template int convert_p<S, F64>(dwa_ctx*, void*, const void*, size_t, double);                 \
-  template int convert_p<S, F32>(dwa_ctx*, void*, const void*, size_t, double);                 \
-  template int convert_p<S, BF16>(dwa_ctx*, void*, const void*, size_t, double);
+  template int convert_p<S, F64>(dwa_ctx*, void*, const void*, size_t, double, int, const double*); \
+  template int convert_p<S, F32>(dwa_ctx*, void*, const void*, size_t, double, int, const double*); \
+  template int convert_p<S, BF16>(dwa_ctx*, void*, const void*, size_t, double, int, const double*);
 
 }  // namespace dwa

@@ -3,6 +3,10 @@
 // every launcher on the storage precision.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
+
 #include "dwa_internal.h"
 
 namespace dwa {
@@ -44,15 +48,22 @@ __device__ double sum_partials_block(const double* part, int n) {
 
 // which: 0 -> qq, a = gamma/qq ; 1 -> zz (bank a), rr (bank b), beta, gamma ;
 //        2 -> init: gamma = sum(a), rr = b2 = sum(b) ; 3 -> aux = sum(a) ; 4 -> rr = sum(a)
+// Block r finalizes field r of a batch (partials packed per field).  A field whose
+// active flag the host has cleared keeps its x and r (a = 0) and restarts p from z.
 __global__ void __launch_bounds__(RED_THREADS) cg_finalize_kernel(DevScalars* s, int which,
                                                                    const double* pa, int na,
                                                                    const double* pb, int nb) {
+  s += blockIdx.x;
+  pa += size_t(blockIdx.x) * na;
+  if (pb) pb += size_t(blockIdx.x) * nb;
   const double A = sum_partials_block(pa, na);
   const double B = (pb != nullptr) ? sum_partials_block(pb, nb) : 0.0;
   if (threadIdx.x != 0) return;
   if (which == 0) {
     s->qq = A;
-    if (!(A > 0.0) || !isfinite(A)) {
+    if (!s->active) {
+      s->a = 0.0;
+    } else if (!(A > 0.0) || !isfinite(A)) {
       s->flags |= 1;
       s->a = 0.0;
     } else {
@@ -61,7 +72,9 @@ __global__ void __launch_bounds__(RED_THREADS) cg_finalize_kernel(DevScalars* s,
   } else if (which == 1) {
     s->zz = A;
     s->rr = B;
-    if (!isfinite(A) || !(s->gamma > 0.0)) {
+    if (!s->active) {
+      s->beta = 0.0;
+    } else if (!isfinite(A) || !(s->gamma > 0.0)) {
       s->flags |= 2;
       s->beta = 0.0;
     } else {
@@ -73,6 +86,7 @@ __global__ void __launch_bounds__(RED_THREADS) cg_finalize_kernel(DevScalars* s,
     s->rr = B;
     s->b2 = B;
     s->flags = 0;
+    s->active = 1;
   } else if (which == 3) {
     s->aux = A;
   } else {
@@ -178,30 +192,110 @@ inline int grid_for(size_t n, int block, int cap = 65536) {
     default: set_error("bad precision"); return DWA_EINVAL; \
   }
 
+namespace {
+// Diagnostics: DWA_BATCH_SERIAL=hop,smix,up1,up2,vec,fin runs the named batched kernels
+// as one launch per field (same arithmetic, no cross-field concurrency).
+bool serial(const char* what) {
+  const char* e = std::getenv("DWA_BATCH_SERIAL");
+  return e && std::strstr(e, what) != nullptr;
+}
+template <typename T>
+T* fshift(T* p, int prec, size_t n, int f) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<std::conditional_t<std::is_const_v<T>, const char, char>*>(p) +
+                                  elem_bytes(prec) * n * f)
+           : p;
+}
+}  // namespace
+
 int launch_hop(dwa_ctx* ctx, int prec, const HopOp& op, int* nblocks_out) {
+  if (op.nrhs > 1 && (serial("hop,") || serial("hopall") || (op.partials && serial("hopp")) ||
+                      (!op.partials && serial("hopn")))) {
+    const size_t n = field_elems(ctx);
+    for (int f = 0; f < op.nrhs; ++f) {
+      HopOp o = op;
+      o.nrhs = 1;
+      o.in = fshift(op.in, prec, n, f);
+      o.out = fshift(op.out, prec, n, f);
+      o.pre = fshift(op.pre, prec, n, f);
+      o.post = fshift(op.post, prec, n, f);
+      int nb = 0;
+      if (op.partials) {
+        // per-field partial counts are the same for every field: find them first
+        HopOp probe = o;
+        probe.partials = op.partials;
+        if (f == 0) {
+          int rc = launch_hop(ctx, prec, probe, &nb);
+          if (rc) return rc;
+          if (nblocks_out) *nblocks_out = nb;
+          continue;
+        }
+        o.partials = op.partials + size_t(f) * (nblocks_out ? *nblocks_out : 0);
+      }
+      int rc = launch_hop(ctx, prec, o, &nb);
+      if (rc) return rc;
+      if (nblocks_out) *nblocks_out = nb;
+    }
+    return DWA_OK;
+  }
   DWA_DISPATCH(prec, launch_hop_p<S_>(ctx, op, nblocks_out));
 }
 int launch_smix(dwa_ctx* ctx, int prec, int mix, void* out, const void* in, const void* post,
-                double post_coef, int nslices, double* partials, int* nblocks_out) {
+                double post_coef, int nslices, double* partials, int* nblocks_out, int nrhs) {
+  if (nrhs > 1 && serial("smix")) {
+    const size_t n = field_elems(ctx);
+    for (int f = 0; f < nrhs; ++f) {
+      int nb = 0;
+      int rc = launch_smix(ctx, prec, mix, fshift(out, prec, n, f), fshift(in, prec, n, f),
+                           fshift(post, prec, n, f), post_coef, nslices,
+                           partials ? partials + size_t(f) * ((6 * ctx->Vh + 255) / 256) : nullptr, &nb, 1);
+      if (rc) return rc;
+      if (nblocks_out) *nblocks_out = nb;
+    }
+    return DWA_OK;
+  }
   DWA_DISPATCH(prec, launch_smix_p<S_>(ctx, mix, out, in, post, post_coef, nslices, partials,
-                                       nblocks_out));
+                                       nblocks_out, nrhs));
 }
 int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
-                      const void* q, const DevScalars* s, double* partials, int* nblocks, bool adj) {
-  DWA_DISPATCH(prec, launch_update1_p<S_>(ctx, x, r, w, p, q, s, partials, nblocks, adj));
+                      const void* q, const DevScalars* s, double* partials, int* nblocks, bool adj,
+                      int nrhs) {
+  if (nrhs > 1 && serial("up1")) {
+    const size_t n = field_elems(ctx);
+    for (int f = 0; f < nrhs; ++f) {
+      int nb = 0;
+      int rc = launch_cg_update1(ctx, prec, fshift(x, xacc_prec(prec), n, f), fshift(r, prec, n, f),
+                                 fshift(w, prec, n, f), fshift(p, prec, n, f), fshift(q, prec, n, f), s + f,
+                                 partials + size_t(f) * ((6 * ctx->Vh + 255) / 256), &nb, adj, 1);
+      if (rc) return rc;
+      if (nblocks) *nblocks = nb;
+    }
+    return DWA_OK;
+  }
+  DWA_DISPATCH(prec, launch_update1_p<S_>(ctx, x, r, w, p, q, s, partials, nblocks, adj, nrhs));
 }
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
-                      const DevScalars* s, bool adj) {
-  DWA_DISPATCH(prec, launch_update2_p<S_>(ctx, p, u, z, s, adj));
+                      const DevScalars* s, bool adj, int nrhs) {
+  if (nrhs > 1 && serial("up2")) {
+    const size_t n = field_elems(ctx);
+    for (int f = 0; f < nrhs; ++f) {
+      int rc = launch_cg_update2(ctx, prec, fshift(p, prec, n, f), fshift(u, prec, n, f),
+                                 fshift(z, prec, n, f), s + f, adj, 1);
+      if (rc) return rc;
+    }
+    return DWA_OK;
+  }
+  DWA_DISPATCH(prec, launch_update2_p<S_>(ctx, p, u, z, s, adj, nrhs));
 }
-int launch_norm2(dwa_ctx* ctx, int prec, const void* x, size_t n, double* partials, int* nblocks) {
-  DWA_DISPATCH(prec, norm2_p<S_>(ctx, x, n, partials, nblocks));
+int launch_norm2(dwa_ctx* ctx, int prec, const void* x, size_t n, double* partials, int* nblocks,
+                 int nrhs) {
+  DWA_DISPATCH(prec, norm2_p<S_>(ctx, x, n, partials, nblocks, nrhs));
 }
-int launch_axpby(dwa_ctx* ctx, int prec, void* y, double a, const void* x, double b, size_t n) {
-  DWA_DISPATCH(prec, axpby_p<S_>(ctx, y, a, x, b, n));
+int launch_axpby(dwa_ctx* ctx, int prec, void* y, double a, const void* x, double b, size_t n,
+                 int nrhs, const double* ab) {
+  DWA_DISPATCH(prec, axpby_p<S_>(ctx, y, a, x, b, n, nrhs, ab));
 }
-int launch_zero(dwa_ctx* ctx, int prec, void* p, size_t n) {
-  DWA_DISPATCH(prec, zero_p<S_>(ctx, p, n));
+int launch_zero(dwa_ctx* ctx, int prec, void* p, size_t n, int nrhs) {
+  DWA_DISPATCH(prec, zero_p<S_>(ctx, p, n, nrhs));
 }
 int launch_pack5(dwa_ctx* ctx, int prec, void* dst, const void* src, int parity, int nslices) {
   DWA_DISPATCH(prec, pack5_p<S_>(ctx, dst, src, parity, nslices));
@@ -214,19 +308,28 @@ int launch_pack_links(dwa_ctx* ctx, int prec, void* dst, const void* src) {
 }
 namespace {
 template <typename SO>
-int convert_from(dwa_ctx* ctx, void* out, int prec_in, const void* in, size_t n, double scale) {
-  DWA_DISPATCH(prec_in, (convert_p<SO, S_>(ctx, out, in, n, scale)));
+int convert_from(dwa_ctx* ctx, void* out, int prec_in, const void* in, size_t n, double scale,
+                 int nrhs, const double* scales) {
+  DWA_DISPATCH(prec_in, (convert_p<SO, S_>(ctx, out, in, n, scale, nrhs, scales)));
 }
 }  // namespace
 int launch_convert(dwa_ctx* ctx, int prec_out, void* out, int prec_in, const void* in, size_t n,
-                   double scale) {
-  DWA_DISPATCH(prec_out, convert_from<S_>(ctx, out, prec_in, in, n, scale));
+                   double scale, int nrhs, const double* scales) {
+  DWA_DISPATCH(prec_out, convert_from<S_>(ctx, out, prec_in, in, n, scale, nrhs, scales));
 }
 
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* pa, int na,
-                       const double* pb, int nb) {
-  hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(RED_THREADS), 0, ctx->stream, s, which, pa,
-                     na, pb, nb);
+                       const double* pb, int nb, int nrhs) {
+  if (nrhs > 1 && serial("fin")) {
+    for (int f = 0; f < nrhs; ++f) {
+      int rc = launch_cg_finalize(ctx, which, s + f, pa + size_t(f) * na, na,
+                                  pb ? pb + size_t(f) * nb : nullptr, nb, 1);
+      if (rc) return rc;
+    }
+    return DWA_OK;
+  }
+  hipLaunchKernelGGL(cg_finalize_kernel, dim3(nrhs), dim3(RED_THREADS), 0, ctx->stream, s, which,
+                     pa, na, pb, nb);
   return hip_fail(hipGetLastError(), "finalize launch");
 }
 

@@ -94,6 +94,13 @@ def lib():
         "dwa_propagator_adjoint": (c_int, [P, P, P, POINTER(c_double), POINTER(c_double),
                                            POINTER(c_double), POINTER(c_double), P, P, P,
                                            POINTER(dwa_solve_opts), POINTER(dwa_solve_stats)]),
+        "dwa_reserve_batch": (c_int, [P, c_int]),
+        "dwa_apply_Dbb_batch": (c_int, [P, c_int, c_int, P, P, POINTER(c_double)]),
+        "dwa_propagator_batch": (c_int, [P, c_int, P, P, POINTER(dwa_solve_opts),
+                                         POINTER(dwa_solve_stats)]),
+        "dwa_propagator_multi": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int), POINTER(c_void_p),
+                                         POINTER(c_void_p), POINTER(dwa_solve_opts),
+                                         POINTER(dwa_solve_stats)]),
         "dwa_strerror": (ctypes.c_char_p, [c_int]),
         "dwa_last_error": (ctypes.c_char_p, []),
         "dwa_debug_smatrix": (c_int, [POINTER(dwa_params), c_int, POINTER(c_double)]),
@@ -334,6 +341,25 @@ class Context:
             out["c"] = gc
         return out
 
+    def reserve_batch(self, nmax):
+        check(lib().dwa_reserve_batch(self._h, int(nmax)))
+
+    def apply_Dbb_batch(self, x, prec="f64", out=None, norms=False):
+        """D_bb on a batch of half fields x [n, ...] (dwa_apply_Dbb_batch); with norms,
+        also |out|^2 per field from the kernel's partial sums."""
+        if out is None:
+            out = _torch().empty_like(x)
+        n = int(x.shape[0])
+        nrm = (c_double * n)() if norms else None
+        check(lib().dwa_apply_Dbb_batch(self._h, PREC[prec], n, _ptr(out), _ptr(x), nrm))
+        return (out, [nrm[i] for i in range(n)]) if norms else out
+
+    def propagator_batch(self, eta, **kw):
+        """y_1 for a batch of sources eta [n, V, 4, 3] (dwa_propagator_batch).
+        Returns (y1 [n, V, 4, 3], list of stats dicts, status)."""
+        y, st, rc = propagator_multi([(self, eta)], **kw)
+        return y[0], st[0], rc
+
     def set_alpha(self, alpha):
         check(lib().dwa_set_alpha(self._h, float(alpha)))
         self.params.alpha = float(alpha)
@@ -351,3 +377,35 @@ class Context:
         rc = check(lib().dwa_alpha_sweep(self._h, a.ctypes.data_as(POINTER(c_double)), n, _ptr(y1),
                                          _ptr(eta), byref(o), st), allow=(DWA_ENOCONV,))
         return y1, [st[i].as_dict() for i in range(n)], rc
+
+
+def propagator_multi(batches, **kw):
+    """Batched propagators over several contexts in one solve (dwa_propagator_multi).
+    batches: list of (Context, eta [n_i, V_i, 4, 3]).  Returns (list of y1 batches,
+    list of per-context stats lists, status)."""
+    torch = _torch()
+    nctx = len(batches)
+    ctxs = (c_void_p * nctx)()
+    nr = (c_int * nctx)()
+    ys, etas = [], []
+    for i, (ctx, eta) in enumerate(batches):
+        if eta.dim() != 4:
+            raise ValueError("eta must be [n, V, 4, 3]")
+        ctx._check_canon(eta[0], (ctx.V, 4, 3))
+        if not eta.is_contiguous():
+            raise ValueError("eta must be contiguous")
+        ctxs[i] = ctx._h.value
+        nr[i] = eta.shape[0]
+        ys.append(torch.zeros_like(eta))
+        etas.append(eta)
+    yp = (c_void_p * nctx)(*[y.data_ptr() for y in ys])
+    ep = (c_void_p * nctx)(*[e.data_ptr() for e in etas])
+    o = Context.opts(**kw)
+    total = sum(nr)
+    st = (dwa_solve_stats * total)()
+    rc = check(lib().dwa_propagator_multi(ctxs, nctx, nr, yp, ep, byref(o), st), allow=(DWA_ENOCONV,))
+    out, k = [], 0
+    for i in range(nctx):
+        out.append([st[k + j].as_dict() for j in range(nr[i])])
+        k += nr[i]
+    return ys, out, rc

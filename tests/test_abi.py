@@ -63,6 +63,9 @@ def test_calls_reject_null_context():
     assert L.dwa_alpha_sweep(None, None, 1, None, None, None, None) == dwa.DWA_EINVAL
     assert L.dwa_propagator_adjoint(None, None, None, None, None, None, None, None, None, None,
                                     None, None) == dwa.DWA_EINVAL
+    assert L.dwa_reserve_batch(None, 4) == dwa.DWA_EINVAL
+    assert L.dwa_propagator_batch(None, 1, None, None, None, None) == dwa.DWA_EINVAL
+    assert L.dwa_propagator_multi(None, 0, None, None, None, None, None) == dwa.DWA_EINVAL
     assert L.dwa_apply_Dbb(None, 0, None, None) == dwa.DWA_EINVAL
     assert L.dwa_set_links(None, None) == dwa.DWA_EINVAL
     assert L.dwa_propagator(None, None, None, None, None, None) == dwa.DWA_EINVAL
