@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
     ap.add_argument("--no-sweep", action="store_true", help="skip the alpha sweep")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched 3-lattice x 12-source solve")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 512 MiB device copy (scale reference for HBM counters)")
@@ -211,6 +213,11 @@ def main():
         log(f"  mixed at alpha {alphas[best]}: {sweep['mixed_at_best_alpha']['time_s']} s, "
             f"{stb['iters']} iters")
 
+    # --- batched solve: 3 lattices x 12 spin-colour sources against 36 single solves -
+    batch = None
+    if not args.no_batch:
+        batch = batch_bench(torch, dwa, synth, dev, stream, args)
+
     # --- CPU oracle on a bounded sample ---------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -253,10 +260,94 @@ def main():
         "dbb": {p: {k: round(v, 2) for k, v in kern[p].items()} for p in kern},
         "roofline": roofline,
         "alpha_sweep": sweep,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)
     ctx.close()
+
+
+def batch_bench(torch, dwa, synth, dev, stream, args):
+    """The batched workload: 8^4 / Ls 8, 12^3x24 / Ls 12 and 16^3x32 / Ls 16 with the 12
+    spin-colour point sources each, FP32 inner solves to 1e-10, all 36 systems in one
+    dwa_propagator_multi call, against the same 36 systems solved one at a time.  Also
+    the batched D_bb of 12 FP32 fields on 16^3x32 against 12 single applications."""
+    bw = synth.BATCH_WORKLOAD
+    kw = dict(tol=args.tol, inner_prec="f32", delta=0.1, check_every=args.check_every)
+    batches = []
+    for k, lat in enumerate(bw["lattices"]):
+        dims, Ls = lat["dims"], lat["Ls"]
+        ctx = dwa.Context(dims, Ls, bw["M5"], bw["m"], bw["alpha"], bw["b"], bw["c"])
+        ctx.set_links(torch.from_numpy(synth.su3_field(dims, bw["spread"], bw["seed"] + k)).to(dev))
+        ctx.reserve_batch(12)
+        eta = torch.from_numpy(np.stack([synth.point_source(dims, 0, j // 3, j % 3)
+                                         for j in range(12)])).to(dev)
+        batches.append((ctx, eta))
+    log("batch: 3 lattices x 12 sources, FP32 inner (warmup)")
+    dwa.propagator_multi(batches, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ys, sts, rc = dwa.propagator_multi(batches, **kw)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"  batched: {t_batch:.3f} s, status {rc}")
+    for ctx, eta in batches:  # warm each context's single-solve path
+        ctx.propagator(eta[0].contiguous(), **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq, seq_iters = [], []
+    for ctx, eta in batches:
+        ylat, it = [], []
+        for j in range(12):
+            y, st, _ = ctx.propagator(eta[j].contiguous(), **kw)
+            ylat.append(y)
+            it.append(st["iters"])
+        seq.append(ylat)
+        seq_iters.append(it)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"  sequential: {t_seq:.3f} s")
+    diff = max(float(torch.linalg.vector_norm(ys[i][j] - seq[i][j]) / torch.linalg.vector_norm(seq[i][j]))
+               for i in range(3) for j in range(12))
+    lat = []
+    for (ctx, _), st, it in zip(batches, sts, seq_iters):
+        lat.append({"dims": list(ctx.dims), "Ls": ctx.Ls,
+                    "batch_iters": [s["iters"] for s in st], "single_iters": it,
+                    "max_rel_resid": max(s["rel_resid"] for s in st)})
+    # batched D_bb, 12 FP32 fields on the largest lattice
+    ctx = batches[2][0]
+    x = torch.stack([ctx.half_field("f32") for _ in range(12)]).contiguous()
+    x.copy_(torch.randn(x.shape, dtype=x.dtype, device=dev))
+    out = torch.empty_like(x)
+    ctx.apply_Dbb_batch(x, "f32", out=out)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(5):
+        ctx.apply_Dbb_batch(x, "f32", out=out)
+    end.record(stream)
+    end.synchronize()
+    batch_ms = start.elapsed_time(end) / 5
+    start.record(stream)
+    for _ in range(5):
+        for j in range(12):
+            ctx.apply_Dbb(x[j], "f32", out=out[j])
+    end.record(stream)
+    end.synchronize()
+    single_ms = start.elapsed_time(end) / 5
+    Vh = ctx.Vh
+    S = ctx.Ls * 12 * Vh * 8
+    Lb = 4 * 2 * Vh * 9 * 8
+    dbb = {"fields": 12, "batched_ms": round(batch_ms, 3), "single_x12_ms": round(single_ms, 3),
+           "batched_gbs_per_field_model": round(12 * (5 * S + 2 * Lb) / batch_ms / 1e6, 1)}
+    log(f"  D_bb x12 FP32 16^3x32: batched {batch_ms:.3f} ms, 12 single {single_ms:.3f} ms")
+    for c, _ in batches:
+        c.close()
+    return {"workload": "8^4/Ls8 + 12^3x24/Ls12 + 16^3x32/Ls16, 12 point sources each, "
+                        f"spread {bw['spread']}, alpha {bw['alpha']}, m {bw['m']}, FP32 inner, "
+                        f"tol {args.tol}",
+            "status": rc, "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
+            "speedup": round(t_seq / t_batch, 3), "max_y1_rel_diff_batch_vs_single": diff,
+            "lattices": lat, "dbb_batch": dbb}
 
 
 def measured_traffic(kernel):

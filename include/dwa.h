@@ -233,9 +233,11 @@ int dwa_apply_Dbb_batch(dwa_ctx *ctx, int prec, int nrhs, void *out, const void 
  * batch shares each kernel launch (the fused hop reads a chunk's links once per XCD for
  * all fields), and the CGNE iteration body is replayed from a hipGraph between host
  * convergence checks.  opts->inner_prec = DWA_F64 runs FP64 CGNE; DWA_F32 / DWA_BF16
- * run FP64 defect correction around batched low-precision CGNE (opts->mixed_mode is
- * not used).  stats (may be NULL) receives nrhs entries.  nrhs must not exceed the
- * reservation.  Returns DWA_ENOCONV if any field missed the tolerance. */
+ * run batched low-precision CGNE with FP64 reliable updates (DWA_MIXED_RELIABLE: the
+ * live fields of a context are updated together, at a check where one of them has
+ * reduced its residual by opts->delta) or FP64 defect correction (DWA_MIXED_DEFECT).
+ * stats (may be NULL) receives nrhs entries; outer counts the FP64 updates.  nrhs must
+ * not exceed the reservation.  Returns DWA_ENOCONV if any field missed the tolerance. */
 int dwa_propagator_batch(dwa_ctx *ctx, int nrhs, void *y1, const void *eta,
                          const dwa_solve_opts *opts, dwa_solve_stats *stats);
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -535,6 +536,9 @@ struct BatchSys {
   long long n_dbb = 0;
 };
 
+// Called at every host check (k > 0) for each system; last is set at maxiter.
+using BatchHook = std::function<int(BatchSys&, int k, bool last)>;
+
 void batch_sys_vectors(BatchSys& b) {
   BatchWs& w = b.ctx->batch;
   if (b.prec == DWA_F64) {
@@ -556,19 +560,41 @@ int batch_freeze(BatchSys& b, int k, hipStream_t st) {
   return DWA_OK;
 }
 
-// One CGLS iteration of every system (the body that is captured into a hipGraph).
-int batch_iteration(std::vector<BatchSys>& S) {
+// The CGLS iteration is split at the point where the host looks at the scalars, right
+// after x and r have been updated (as in the single-field reliable solver):
+//   first half:  q = A p, a = gamma / |q|^2, x += a p, r -= a q, |r|^2, w = premix of r
+//   second half: z = A^dag r, beta = |z|^2 / gamma, p = z + beta p, u = premix of p
+// The graph body is (second half, first half); the first iteration runs its first half
+// eagerly.  A host check after k bodies therefore sees the residual of k updates of x.
+int batch_first_half(BatchSys& b) {
+  dwa_ctx* ctx = b.ctx;
+  DevScalars* sc = ctx->batch.d_scal;
+  int nbA = 0, nbB = 0;
+  DWA_TRY(dbb_from_premix(ctx, b.prec, b.q, b.p, b.u, b.t, bbank(ctx, 0), &nbA, b.nr));
+  DWA_TRY(launch_cg_finalize(ctx, 0, sc, bbank(ctx, 0), nbA, nullptr, 0, b.nr));
+  DWA_TRY(launch_cg_update1(ctx, b.prec, b.x, b.r, b.w, b.p, b.q, sc, bbank(ctx, 1), &nbB, false, b.nr));
+  DWA_TRY(launch_cg_finalize(ctx, 4, sc, bbank(ctx, 1), nbB, nullptr, 0, b.nr));
+  b.n_dbb += b.nr;
+  return DWA_OK;
+}
+
+int batch_second_half(BatchSys& b) {
+  dwa_ctx* ctx = b.ctx;
+  DevScalars* sc = ctx->batch.d_scal;
+  int nbZ = 0;
+  DWA_TRY(dbbdag_from_premix(ctx, b.prec, b.z, b.r, b.w, b.t, bbank(ctx, 0), &nbZ, b.nr));
+  // (rr is not needed here: the next first half recomputes it before any check)
+  DWA_TRY(launch_cg_finalize(ctx, 1, sc, bbank(ctx, 0), nbZ, nullptr, 0, b.nr));
+  DWA_TRY(launch_cg_update2(ctx, b.prec, b.p, b.u, b.z, sc, false, b.nr));
+  b.n_dbb += b.nr;
+  return DWA_OK;
+}
+
+// The replayed body: one iteration of every system.
+int batch_body(std::vector<BatchSys>& S) {
   for (auto& b : S) {
-    dwa_ctx* ctx = b.ctx;
-    DevScalars* sc = ctx->batch.d_scal;
-    int nbA = 0, nbB = 0, nbZ = 0;
-    DWA_TRY(dbb_from_premix(ctx, b.prec, b.q, b.p, b.u, b.t, bbank(ctx, 0), &nbA, b.nr));
-    DWA_TRY(launch_cg_finalize(ctx, 0, sc, bbank(ctx, 0), nbA, nullptr, 0, b.nr));
-    DWA_TRY(launch_cg_update1(ctx, b.prec, b.x, b.r, b.w, b.p, b.q, sc, bbank(ctx, 1), &nbB, false, b.nr));
-    DWA_TRY(dbbdag_from_premix(ctx, b.prec, b.z, b.r, b.w, b.t, bbank(ctx, 0), &nbZ, b.nr));
-    DWA_TRY(launch_cg_finalize(ctx, 1, sc, bbank(ctx, 0), nbZ, bbank(ctx, 1), nbB, b.nr));
-    DWA_TRY(launch_cg_update2(ctx, b.prec, b.p, b.u, b.z, sc, false, b.nr));
-    b.n_dbb += 2LL * b.nr;
+    DWA_TRY(batch_second_half(b));
+    DWA_TRY(batch_first_half(b));
   }
   return DWA_OK;
 }
@@ -576,10 +602,13 @@ int batch_iteration(std::vector<BatchSys>& S) {
 // CGLS on every field of every system at once.  All work runs on stream st (the
 // contexts' streams point at it for the duration).  Between host checks the iteration
 // body of all systems is replayed from one hipGraph (no memset nodes: kernels only).
-// A field stops (is frozen on the device) when its recursive residual reaches its
-// tolerance; iteration counts are those of the check at which it stopped.
+// Host checks come every check_every iterations.  Without a hook a field stops (is
+// frozen on the device) when its recursive residual reaches its tolerance.  With a
+// hook, the hook decides at every check (reliable updates): it is called once per
+// system with the scalars of its fields on the host.  Iteration counts are those of
+// the check at which a field stopped.
 int cgls_multi(std::vector<BatchSys>& S, hipStream_t st, int maxiter, int check_every,
-               bool use_graph) {
+               bool use_graph, const BatchHook& hook) {
   if (check_every < 1) check_every = 1;
   for (auto& b : S) {
     dwa_ctx* ctx = b.ctx;
@@ -613,26 +642,15 @@ int cgls_multi(std::vector<BatchSys>& S, hipStream_t st, int maxiter, int check_
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
   };
-  if (use_graph) {
-    DWA_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-    const int rc = batch_iteration(S);
-    const hipError_t e = hipStreamEndCapture(st, &graph);
-    if (rc != DWA_OK) {
-      cleanup();
-      return rc;
+  auto body = [&]() -> int {
+    if (exec) {
+      const hipError_t e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess) return hip_fail(e, "graph launch");
+      for (auto& b : S) b.n_dbb += 2LL * b.nr;
+      return DWA_OK;
     }
-    if (e != hipSuccess) {
-      cleanup();
-      return hip_fail(e, "end capture");
-    }
-    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ei != hipSuccess) {
-      cleanup();
-      return hip_fail(ei, "graph instantiate");
-    }
-    // the capture counted one iteration per system; the replays count themselves
-    for (auto& b : S) b.n_dbb -= 2LL * b.nr;
-  }
+    return batch_body(S);
+  };
   int k = 0;
   for (;;) {
     // host check: read every system's scalars
@@ -662,41 +680,75 @@ int cgls_multi(std::vector<BatchSys>& S, hipStream_t st, int maxiter, int check_
         if (h.flags) {
           b.breakdown[f] = 1;
           stop = true;
-        } else if (h.b2 == 0.0 || h.rr <= b.tol[f] * b.tol[f] * h.b2) {
+        } else if (!hook && (h.b2 == 0.0 || h.rr <= b.tol[f] * b.tol[f] * h.b2)) {
           b.converged[f] = 1;
           stop = true;
         }
         if (stop) {
           b.iters[f] = k;
-          int rc = batch_freeze(b, f, st);
+          const int rc = batch_freeze(b, f, st);
           if (rc != DWA_OK) {
             cleanup();
             return rc;
           }
-        } else {
-          ++active;
         }
       }
-    }
-    if (active == 0 || k >= maxiter) break;
-    const int nrun = std::min(check_every, maxiter - k);
-    for (int i = 0; i < nrun; ++i) {
-      if (exec) {
-        const hipError_t e = hipGraphLaunch(exec, st);
-        if (e != hipSuccess) {
-          cleanup();
-          return hip_fail(e, "graph launch");
-        }
-        for (auto& b : S) b.n_dbb += 2LL * b.nr;
-      } else {
-        const int rc = batch_iteration(S);
+      if (hook && k > 0) {
+        const int rc = hook(b, k, k >= maxiter);
         if (rc != DWA_OK) {
           cleanup();
           return rc;
         }
       }
+      for (int f = 0; f < b.nr; ++f) active += w.h_active[f] ? 1 : 0;
     }
-    k += nrun;
+    if (active == 0 || k >= maxiter) break;
+    if (k == 0) {
+      // first half of the first iteration, eagerly; then capture the body
+      for (auto& b : S) {
+        const int rc = batch_first_half(b);
+        if (rc != DWA_OK) {
+          cleanup();
+          return rc;
+        }
+      }
+      k = 1;
+      if (use_graph) {
+        DWA_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+        const int rc = batch_body(S);
+        const hipError_t e = hipStreamEndCapture(st, &graph);
+        if (rc != DWA_OK) {
+          cleanup();
+          return rc;
+        }
+        if (e != hipSuccess) {
+          cleanup();
+          return hip_fail(e, "end capture");
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+          cleanup();
+          return hip_fail(ei, "graph instantiate");
+        }
+        // the capture counted one iteration per system; the replays count themselves
+        for (auto& b : S) b.n_dbb -= 2LL * b.nr;
+      }
+    } else {
+      const int rc = body();
+      if (rc != DWA_OK) {
+        cleanup();
+        return rc;
+      }
+      ++k;
+    }
+    while (k % check_every != 0 && k < maxiter) {
+      const int rc = body();
+      if (rc != DWA_OK) {
+        cleanup();
+        return rc;
+      }
+      ++k;
+    }
   }
   for (auto& b : S)
     for (int f = 0; f < b.nr; ++f)
@@ -1440,11 +1492,120 @@ int dwa_propagator_multi(dwa_ctx* const* ctxs, int nctx, const int* nrhs, void* 
         S[i].tol.assign(nrhs[i], o->tol);
         batch_sys_vectors(S[i]);
       }
-      DWA_TRY(cgls_multi(S, st, o->maxiter, o->check_every, true));
+      DWA_TRY(cgls_multi(S, st, o->maxiter, o->check_every, true, BatchHook{}));
       for (int i = 0; i < nctx; ++i) {
         iters[i] = S[i].iters;
         fp64_conv[i] = S[i].converged;
       }
+    } else if (o->mixed_mode != DWA_MIXED_DEFECT) {
+      // reliable updates: one low-precision CGLS per field for the whole solve, the
+      // scheme of the single-field solver.  At a host check where some field of a
+      // context has reduced its low-precision residual by delta (or is predicted to
+      // have converged), every live field of that context folds x_l into X, gets its
+      // true FP64 residual, and continues from it at unit norm with p and gamma
+      // rescaled.  (One batched FP64 D_bb serves all fields of the context, so they
+      // are updated together.)
+      const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
+      std::vector<std::vector<double>> scale(nctx), rmax(nctx), last(nctx);
+      std::vector<std::vector<int>> stall(nctx);
+      std::vector<BatchSys> S(nctx);
+      for (int i = 0; i < nctx; ++i) {
+        dwa_ctx* ctx = ctxs[i];
+        BatchWs& w = ctx->batch;
+        const int nr = nrhs[i];
+        const size_t n = field_elems(ctx);
+        scale[i] = bnorm[i];
+        rmax[i].assign(nr, 1.0);
+        last[i].assign(nr, 1.0);
+        stall[i].assign(nr, 0);
+        DWA_TRY(launch_zero(ctx, DWA_F64, w.f64[B_X], n, nr));
+        S[i].ctx = ctx;
+        S[i].nr = nr;
+        S[i].prec = inner;
+        S[i].x = w.xacc;
+        S[i].rhs = w.lo[inner][BL_RHS];
+        S[i].tol.assign(nr, 0.0);
+        for (int f = 0; f < nr; ++f) {
+          w.h_coef[f] = bnorm[i][f] > 0.0 ? 1.0 / bnorm[i][f] : 0.0;
+          if (bnorm[i][f] == 0.0) {
+            S[i].tol[f] = -1.0;
+            rel[i][f] = 0.0;
+          }
+        }
+        batch_sys_vectors(S[i]);
+        DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
+        DWA_TRY(launch_convert(ctx, inner, w.lo[inner][BL_RHS], DWA_F64, w.f64[B_PHI], n, 0.0, nr, w.d_coef));
+        // the pinned coefficients are rewritten below only after a synchronisation
+        DWA_HIP(hipStreamSynchronize(st), "coef sync");
+      }
+      const BatchHook hook = [&](BatchSys& b, int k, bool at_end) -> int {
+        const int i = int(&b - S.data());
+        dwa_ctx* ctx = b.ctx;
+        BatchWs& w = ctx->batch;
+        const int nr = b.nr;
+        const size_t n = field_elems(ctx);
+        bool trig = at_end;
+        for (int f = 0; f < nr; ++f) {
+          if (!w.h_active[f]) continue;
+          const double rl = std::sqrt(w.h_scal[f].rr);
+          if (rl <= delta * rmax[i][f] || rl * scale[i][f] / bnorm[i][f] <= 0.5 * o->tol) trig = true;
+        }
+        if (!trig) return DWA_OK;
+        // X += scale x_l (FP64) for the live fields, x_l = 0, true residuals
+        std::vector<int> live(nr);
+        for (int f = 0; f < nr; ++f) {
+          live[f] = w.h_active[f];
+          w.h_coef[f] = live[f] ? scale[i][f] : 0.0;
+        }
+        DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
+        DWA_TRY(launch_convert(ctx, DWA_F64, w.f64[B_OPB], xacc_prec(inner), w.xacc, n, 0.0, nr, w.d_coef));
+        DWA_TRY(launch_axpby(ctx, DWA_F64, w.f64[B_X], 1.0, w.f64[B_OPB], 1.0, n, nr));
+        DWA_TRY(launch_zero(ctx, xacc_prec(inner), w.xacc, n, nr));
+        std::vector<double> r2(nr);
+        DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));  // synchronises
+        std::vector<double> fac(nr, 1.0);
+        for (int f = 0; f < nr; ++f) {
+          if (!live[f]) continue;
+          const double r = std::sqrt(r2[f]) / bnorm[i][f];
+          rel[i][f] = r;
+          outer[i][f] += 1;
+          bool stop = false;
+          if (r <= o->tol) {
+            b.converged[f] = 1;
+            stop = true;
+          } else {
+            if (!(r < 0.9 * last[i][f])) stop = ++stall[i][f] >= 3;
+            else stall[i][f] = 0;
+            last[i][f] = r;
+          }
+          if (stop) {
+            b.iters[f] = k;
+            DWA_TRY(batch_freeze(b, f, st));
+            continue;
+          }
+          const double ns = r * bnorm[i][f];
+          fac[f] = scale[i][f] / ns;
+          scale[i][f] = ns;
+          rmax[i][f] = 1.0;
+        }
+        // continue in the new units: p *= fac, gamma *= fac^2, r_l = RES / scale
+        for (int f = 0; f < nr; ++f) {
+          w.h_coef[2 * f] = fac[f];
+          w.h_coef[2 * f + 1] = 0.0;
+          w.h_coef[2 * nr + f] = fac[f] * fac[f];
+          w.h_coef[3 * nr + f] = 1.0 / scale[i][f];
+        }
+        DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * 4 * nr, hipMemcpyHostToDevice, st),
+                "coef upload");
+        DWA_TRY(launch_axpby(ctx, inner, b.p, 1.0, b.p, 0.0, n, nr, w.d_coef));
+        DWA_TRY(launch_scale_gamma(ctx, w.d_scal, 1.0, nr, w.d_coef + 2 * nr));
+        DWA_TRY(launch_convert(ctx, inner, b.r, DWA_F64, w.f64[B_RES], n, 0.0, nr, w.d_coef + 3 * nr));
+        DWA_TRY(launch_smix(ctx, inner, MIX_G5_IINVT_GINV, b.w, b.r, nullptr, 0.0, ctx->Ls, nullptr, nullptr, nr));
+        DWA_HIP(hipStreamSynchronize(st), "coef sync");
+        return DWA_OK;
+      };
+      DWA_TRY(cgls_multi(S, st, o->maxiter, o->check_every, true, hook));
+      for (int i = 0; i < nctx; ++i) iters[i] = S[i].iters;
     } else {
       // defect correction: FP64 residuals, one batched low-precision CGLS per round
       const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
@@ -1495,7 +1656,7 @@ int dwa_propagator_multi(dwa_ctx* const* ctxs, int nctx, const int* nrhs, void* 
           which.push_back(i);
         }
         if (S.empty() || total >= o->maxiter) break;
-        DWA_TRY(cgls_multi(S, st, o->maxiter - total, o->check_every, true));
+        DWA_TRY(cgls_multi(S, st, o->maxiter - total, o->check_every, true, BatchHook{}));
         int round_max = 0;
         for (size_t j = 0; j < S.size(); ++j) {
           const int i = which[j];

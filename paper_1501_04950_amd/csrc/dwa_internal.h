@@ -340,7 +340,9 @@ int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
 // one block per field: s[r] from partials_a[r * na ...] and partials_b[r * nb ...]
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* partials_a, int na,
                        const double* partials_b, int nb, int nrhs = 1);
-int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f);
+// gamma *= f for nrhs fields (per-field factors fs[k] when fs is given)
+int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f, int nrhs = 1,
+                       const double* fs = nullptr);
 
 // gradient path (adjoint.hip), FP64 SoA fields; "lt" is g5 lambda
 int launch_adj_source(dwa_ctx* ctx, void* f_b, void* f_r, const void* eta_p);

@@ -334,13 +334,14 @@ int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* pa,
 }
 
 namespace {
-__global__ void scale_gamma_kernel(DevScalars* s, double f) {
-  if (threadIdx.x == 0) s->gamma *= f;
+__global__ void scale_gamma_kernel(DevScalars* s, double f, const double* fs) {
+  // field blockIdx.x of a batch, with its own factor when a table is given
+  if (threadIdx.x == 0) s[blockIdx.x].gamma *= fs ? fs[blockIdx.x] : f;
 }
 }  // namespace
 
-int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f) {
-  hipLaunchKernelGGL(scale_gamma_kernel, dim3(1), dim3(64), 0, ctx->stream, s, f);
+int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f, int nrhs, const double* fs) {
+  hipLaunchKernelGGL(scale_gamma_kernel, dim3(nrhs), dim3(64), 0, ctx->stream, s, f, fs);
   return hip_fail(hipGetLastError(), "scale gamma launch");
 }
 

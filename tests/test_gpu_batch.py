@@ -62,21 +62,33 @@ def test_batch_fp64_equals_single_solves():
     ctx.close()
 
 
-@pytest.mark.parametrize("inner", ["f32", "bf16"])
-def test_batch_mixed_precision(inner):
-    """12 sources on 8^3 x 16, Ls = 12 with low-precision inner CGNE and FP64 defect
-    correction: every field reaches 1e-10 and matches the FP64 batch."""
+@pytest.mark.parametrize("inner,mode,delta", [("f32", "reliable", 0.05), ("bf16", "reliable", 0.3),
+                                              ("f32", "defect", 0.1), ("bf16", "defect", 0.1)])
+def test_batch_mixed_precision(inner, mode, delta):
+    """12 sources on 8^3 x 16, Ls = 12 with low-precision inner CGNE and FP64 reliable
+    updates or defect correction: every field reaches 1e-10 and matches the FP64 batch.
+    With reliable updates the iteration counts stay within 10% (+10) of single-source
+    solves with the same options."""
     ctx, w = _ctx("c2_8x8x8x16_ls12", 0.8)
     eta = torch.from_numpy(spin_colour_sources(w["dims"])).to(gpu())
     ctx.reserve_batch(12)
-    say(f"[gpu] batch of 12 on 8^3x16 Ls=12, inner {inner}")
+    say(f"[gpu] batch of 12 on 8^3x16 Ls=12, inner {inner}, {mode}")
+    kw = dict(tol=1e-10, inner_prec=inner, delta=delta, check_every=10, mixed_mode=mode)
     y64, st64, rc64 = ctx.propagator_batch(eta, tol=1e-10, check_every=10)
-    y, st, rc = ctx.propagator_batch(eta, tol=1e-10, inner_prec=inner, delta=0.1, check_every=10)
+    y, st, rc = ctx.propagator_batch(eta, **kw)
     assert rc64 == dwa.DWA_OK and rc == dwa.DWA_OK
-    say("    iters fp64 " + str([s["iters"] for s in st64]) + f" {inner} " + str([s["iters"] for s in st]))
+    say("    iters fp64 " + str([s["iters"] for s in st64]) + f" {inner} " + str([s["iters"] for s in st])
+        + " outer " + str([s["outer"] for s in st]))
     for k in range(12):
         assert st[k]["rel_resid"] <= 1e-10 and st64[k]["rel_resid"] <= 1e-10
         assert rel(y[k], y64[k]) < 1e-7
+    if mode == "reliable":
+        for k in (0, 5, 11):
+            ys, s1, rc1 = ctx.propagator(eta[k].contiguous(), **kw)
+            assert rc1 == dwa.DWA_OK
+            say(f"    field {k}: batch {st[k]['iters']} single {s1['iters']} iterations")
+            assert st[k]["iters"] <= 1.1 * s1["iters"] + 10
+            assert rel(y[k], ys) < 1e-7
     ctx.close()
 
 
