@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
     ap.add_argument("--no-sweep", action="store_true", help="skip the alpha sweep")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default hop tiles instead of running the autotuner")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched 3-lattice x 12-source solve")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -81,6 +83,20 @@ def main():
     ctx.set_links(Ud)
     eta_d = torch.from_numpy(eta).to(dev)
     torch.cuda.synchronize()
+
+    # --- autotuner: tile and block traversal of the fused hop, per precision --------
+    tuning = {}
+    for prec in ("f64", "f32", "bf16"):
+        if args.no_tune:
+            ns, order = ctx.get_tuning(prec)
+            tuning[prec] = {"ns": ns, "order": order, "tuned": False}
+            continue
+        t0 = time.perf_counter()
+        res = ctx.autotune(prec, reps=10)
+        tuning[prec] = {"ns": res["ns"], "order": res["order"], "pair_us": round(res["us"], 2),
+                        "tuned": True, "tune_s": round(time.perf_counter() - t0, 3),
+                        "candidates": [[c["ns"], c["order"], round(c["us"], 2)] for c in res["candidates"]]}
+        log(f"autotune {prec}: ns={res['ns']} order={res['order']} pair {res['us']:.1f} us")
 
     eb = {"f64": 16, "f32": 8, "bf16": 4}
     S = {p: Ls * 12 * Vh * eb[p] for p in eb}
@@ -224,10 +240,11 @@ def main():
         cpu = cpu_baseline(U, dims, Ls, w, args.alpha, fp64)
 
     dom = kern[args.inner]
-    dom_name = f"dwa::hop_mix_kernel<dwa::{args.inner.upper()}, 16, {Ls}, 0, 2, false>"
+    ns_dom = tuning[args.inner]["ns"]
+    dom_name = f"dwa::hop_mix_kernel<dwa::{args.inner.upper()}, {ns_dom}, {Ls}, 0, 2, false>"
     roofline = {
         "bound": "hbm",
-        "kernel": f"hop_mix_kernel<{args.inner.upper()},16,16,0> (fused Wilson hop + N mix)",
+        "kernel": f"hop_mix_kernel<{args.inner.upper()},{ns_dom},{Ls},0> (fused Wilson hop + N mix)",
         "achieved": round(dom["hop_gbs"], 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -259,6 +276,7 @@ def main():
         "speedup_mixed_vs_fp64": round(fp64["time_s"] / mixed_s, 3) if fp64 else None,
         "dbb": {p: {k: round(v, 2) for k, v in kern[p].items()} for p in kern},
         "roofline": roofline,
+        "tuning": tuning,
         "alpha_sweep": sweep,
         "batch": batch,
         "cpu_baseline": cpu,

@@ -163,6 +163,39 @@ int dwa_apply_Dbb_dag(dwa_ctx *ctx, int prec, void *out_b, const void *in_b);
  * out and in must not overlap.  Exposed for measurement and tests. */
 int dwa_apply_hop(dwa_ctx *ctx, int prec, int parity_out, int kind, void *out, const void *in);
 
+/* Tiles and block traversal of the fused hop.  A block of the hop kernel computes ns
+ * consecutive checkerboard sites on all Ls slices (ns = 8, 16 or 32; Ls = 4, 8, 12, 16
+ * have kernels for all three, any other Ls and the dense fallback run 8), and blocks
+ * walk the lattice in one of three orders: 0 = t-slabs (default), 1 = checkerboard
+ * order, 2 = z-planes per XCD.  Only the assignment of sites to blocks changes: every
+ * site's arithmetic is the same, so D_bb and every hop output are bitwise identical
+ * across configurations (CG reductions group their partial sums by block, so solver
+ * scalars can differ in the last bits).  The defaults are ns = 16 for FP64, 32 for
+ * FP32 / BF16, order 0. */
+typedef struct {
+  int prec;  /* storage precision */
+  int ns;    /* sites per block */
+  int order; /* block traversal */
+  double us; /* average time of one hop pair of D_bb (N hop, then G^-1 I^-1 hop with the
+                x term), microseconds; negative if the configuration cannot run here
+                (its LDS tile exceeds the device limit) */
+} dwa_tune_entry;
+
+/* Autotuner: time every configuration of precision prec on this context's lattice
+ * (reps timed pairs each after a warm-up; reps <= 0 means 10) and keep the fastest
+ * for all later calls on the context.  Uses the context's own workspace (no
+ * allocation; its contents are overwritten, nothing else is touched).  entries (host,
+ * may be NULL) receives up to max_entries timings; *n_entries (may be NULL) the
+ * number of configurations timed. */
+int dwa_autotune(dwa_ctx *ctx, int prec, int reps, dwa_tune_entry *entries, int max_entries,
+                 int *n_entries);
+
+/* Set or read the configuration used for precision prec.  dwa_set_tuning rejects a
+ * tile other than 8, 16, 32, an order outside 0..2, a tile other than 8 where the
+ * generic kernel runs, and a tile whose LDS exceeds the device limit (DWA_EINVAL). */
+int dwa_set_tuning(dwa_ctx *ctx, int prec, int ns, int order);
+int dwa_get_tuning(const dwa_ctx *ctx, int prec, int *ns, int *order);
+
 /* Solve D_bb x_b = rhs_b by CG on the normal equations (Sec. 3).  x_b and rhs_b are
  * FP64 black SoA fields.  Returns DWA_OK, DWA_ENOCONV (x_b holds the last iterate) or
  * DWA_EBREAKDOWN.  stats may be NULL. */

@@ -3,7 +3,8 @@
     python -m paper_1501_04950_amd.build
 
 Each source is compiled to an object in parallel (one translation unit per field
-precision carries most of the kernels), then linked into one shared library.  Device
+precision carries the site-local kernels, and one per precision and tile size the fused
+hop), then linked into one shared library.  Device
 code targets gfx950 only, with packed FP32 instructions turned off.
 """
 
@@ -14,8 +15,9 @@ from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = ["csrc/kernels_f64.hip", "csrc/kernels_f32.hip", "csrc/kernels_bf16.hip",
-           "csrc/kernels.hip", "csrc/adjoint.hip", "csrc/api.cpp", "csrc/smat.cpp"]
+SOURCES = ([f"csrc/kernels_hop_{p}_{ns}.hip" for p in ("f64", "f32", "bf16") for ns in (8, 16, 32)]
+           + ["csrc/kernels_f64.hip", "csrc/kernels_f32.hip", "csrc/kernels_bf16.hip",
+              "csrc/kernels.hip", "csrc/adjoint.hip", "csrc/api.cpp", "csrc/smat.cpp"])
 LIB = os.path.join(PKG, "libdwa.so")
 OBJDIR = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

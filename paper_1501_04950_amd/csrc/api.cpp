@@ -53,6 +53,13 @@ int einval(const std::string& msg) {
   } while (0)
 #define DWA_HIP(expr, what) DWA_TRY(hip_fail((expr), what))
 
+// LDS bytes of one fused-hop block (the device code's hop_mix_lds_bytes): the larger of
+// the [Ls][12][ns+1] output tile and the [72][ns] link area, plus [8][ns] neighbours;
+// cbytes is the size of one complex in the kernel's arithmetic (16 FP64, 8 otherwise).
+size_t hop_mix_lds_bytes_host(int ns, int Ls, size_t cbytes) {
+  return std::max(size_t(Ls) * 12 * (ns + 1) * cbytes, size_t(72) * ns * cbytes) + size_t(8) * ns * 4;
+}
+
 void** low_pool(dwa_ctx* ctx, int prec) {
   if (prec == DWA_F32) return ctx->w32;
   if (prec == DWA_BF16) return ctx->w16;
@@ -887,43 +894,54 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
   if ((rc = hip_fail(hipMemcpy(ctx->d_nbr, nbr.data(), sizeof(int) * nbr.size(),
                                hipMemcpyHostToDevice), "upload nbr")))
     return fail(rc);
-  // fused-hop traversal: chunks of NS consecutive checkerboard sites, ordered by
-  // (t-slab, z, t within the slab, y, x) so that a run of blocks on one XCD touches a
-  // compact slab and the t and z neighbours are re-read from L2, not HBM.  Contiguous
-  // ranges of this order go to one XCD (the kernel remaps block ids accordingly).  One
-  // table per block size (8, 16, 32 sites).
-  for (int bi = 0; bi < 3; ++bi) {
-    const int NS = 8 << bi;
-    const long long nchunk = (Vh + NS - 1) / NS;
-    std::vector<int> order(nchunk);
-    for (long long c = 0; c < nchunk; ++c) order[c] = (int)c;
-    // DWA_HOP_ORDER (tuning): "slab" (default), "lex" (checkerboard order), or
-    // "zdom" (XCD k owns z-planes [k Lz/8, (k+1) Lz/8) and walks them t-major)
-    const char* env = std::getenv("DWA_HOP_ORDER");
-    const std::string order_kind = env ? std::string(env) : std::string("slab");
-    if (order_kind != "lex") {
-      const bool zdom = order_kind == "zdom" && Lz % 8 == 0;
-      const int ts = Lt >= 16 ? Lt / 8 : 1;
-      const int zpd = Lz / 8;
-      std::vector<long long> key(nchunk);
-      for (long long c = 0; c < nchunk; ++c) {
-        long long lex = cb2lex[c * NS];
-        long long r = lex;
-        const long long x = r % Lx; r /= Lx;
-        const long long y = r % Ly; r /= Ly;
-        const long long z = r % Lz;
-        const long long t = r / Lz;
-        key[c] = zdom ? ((((z / zpd) * Lt + t) * zpd + z % zpd) * Ly + y) * Lx + x
-                      : ((((t / ts) * Lz + z) * ts + (t % ts)) * Ly + y) * Lx + x;
+  // fused-hop traversals: chunks of NS consecutive checkerboard sites in one of three
+  // orders (HopOrder); contiguous ranges of the order go to one XCD (the kernel remaps
+  // block ids accordingly).  SLAB walks (t-slab, z, t within the slab, y, x) so that a
+  // run of blocks on one XCD touches a compact slab and the t and z neighbours are
+  // re-read from L2, not HBM.  One table per order and tile size.
+  for (int ord = 0; ord < ORDER_COUNT; ++ord)
+    for (int bi = 0; bi < kTileCount; ++bi) {
+      const int NS = kTiles[bi];
+      const long long nchunk = (Vh + NS - 1) / NS;
+      std::vector<int> order(nchunk);
+      for (long long c = 0; c < nchunk; ++c) order[c] = (int)c;
+      if (ord != ORDER_LEX) {
+        const bool zdom = ord == ORDER_ZDOM && Lz % 8 == 0;
+        const int ts = Lt >= 16 ? Lt / 8 : 1;
+        const int zpd = Lz / 8;
+        std::vector<long long> key(nchunk);
+        for (long long c = 0; c < nchunk; ++c) {
+          long long r = cb2lex[c * NS];
+          const long long x = r % Lx; r /= Lx;
+          const long long y = r % Ly; r /= Ly;
+          const long long z = r % Lz;
+          const long long t = r / Lz;
+          key[c] = zdom ? ((((z / zpd) * Lt + t) * zpd + z % zpd) * Ly + y) * Lx + x
+                        : ((((t / ts) * Lz + z) * ts + (t % ts)) * Ly + y) * Lx + x;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
       }
-      std::stable_sort(order.begin(), order.end(),
-                       [&](int a, int b) { return key[a] < key[b]; });
+      int*& d = ctx->d_blkmap[ord][bi];
+      if ((rc = hip_fail(hipMalloc(&d, sizeof(int) * order.size()), "alloc blkmap"))) return fail(rc);
+      if ((rc = hip_fail(hipMemcpy(d, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice),
+                         "upload blkmap")))
+        return fail(rc);
     }
-    if ((rc = hip_fail(hipMalloc(&ctx->d_blkmap[bi], sizeof(int) * order.size()), "alloc blkmap")))
-      return fail(rc);
-    if ((rc = hip_fail(hipMemcpy(ctx->d_blkmap[bi], order.data(), sizeof(int) * order.size(),
-                                 hipMemcpyHostToDevice), "upload blkmap")))
-      return fail(rc);
+  // default tuning: 32 sites per block for FP32 / BF16 (one 128-byte line per colour-
+  // spin component and slice), 16 for FP64 (whose LDS tile is twice as large), slab
+  // order; DWA_HOP_ORDER=slab|lex|zdom overrides the order (dwa_autotune replaces both)
+  {
+    int ord = ORDER_SLAB;
+    if (const char* e = std::getenv("DWA_HOP_ORDER"))
+      ord = std::string(e) == "lex" ? ORDER_LEX : (std::string(e) == "zdom" ? ORDER_ZDOM : ORDER_SLAB);
+    for (int pr = 0; pr < 3; ++pr) {
+      ctx->tune[pr].ns = pr == DWA_F64 ? 16 : 32;
+      ctx->tune[pr].order = ord;
+    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) == hipSuccess &&
+        lds > 0)
+      ctx->max_lds = size_t(lds);
   }
   // s-matrices
   if ((rc = upload_smatrices(ctx, mix, sweeps, true))) return fail(rc);
@@ -960,7 +978,8 @@ int dwa_destroy(dwa_ctx* ctx) {
   };
   f(ctx->d_nbr);
   f(ctx->d_cb2lex);
-  for (auto p : ctx->d_blkmap) f(p);
+  for (auto& row : ctx->d_blkmap)
+    for (auto p : row) f(p);
   f(ctx->d_mix64);
   f(ctx->d_mix32);
   f(ctx->d_sweep_meta);
@@ -1098,6 +1117,106 @@ int dwa_apply_Dbb_dag(dwa_ctx* ctx, int prec, void* out, const void* in) {
   void** W = low_pool(ctx, prec);
   const bool p64 = prec == DWA_F64;
   return apply_dbbdag(ctx, prec, out, in, W[p64 ? W_OPB : L_OPB], W[p64 ? W_OPR : L_OPR]);
+}
+
+int dwa_set_tuning(dwa_ctx* ctx, int prec, int ns, int order) {
+  DWA_TRY(check_ctx(ctx));
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (!valid_tile(ns)) return einval("tile must be 8, 16 or 32 sites");
+  if (order < 0 || order >= ORDER_COUNT) return einval("order must be 0, 1 or 2");
+  if (!hop_specialised(ctx->Ls, ctx->dense_mix) && ns != 8)
+    return einval("the generic hop kernel (this Ls) runs 8 sites per block");
+  const size_t lds = prec == DWA_F64 ? hop_mix_lds_bytes_host(ns, ctx->Ls, 16) : hop_mix_lds_bytes_host(ns, ctx->Ls, 8);
+  if (std::max(lds, ctx->hop_min_lds) > ctx->max_lds) return einval("tile's LDS exceeds the device limit");
+  ctx->tune[prec].ns = ns;
+  ctx->tune[prec].order = order;
+  return DWA_OK;
+}
+
+int dwa_get_tuning(const dwa_ctx* ctx, int prec, int* ns, int* order) {
+  if (!ctx) return einval("null context");
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (ns) *ns = hop_specialised(ctx->Ls, ctx->dense_mix) ? ctx->tune[prec].ns : 8;
+  if (order) *order = ctx->tune[prec].order;
+  return DWA_OK;
+}
+
+int dwa_autotune(dwa_ctx* ctx, int prec, int reps, dwa_tune_entry* entries, int max_entries,
+                 int* n_entries) {
+  DWA_TRY(check_ctx(ctx));
+  if (!valid_prec(prec)) return einval("bad precision");
+  if (!ctx->links_set) {
+    set_error("set the links first");
+    return DWA_ESTATE;
+  }
+  if (n_entries) *n_entries = 0;
+  if (reps <= 0) reps = 10;
+  const bool p64 = prec == DWA_F64;
+  void** W = p64 ? ctx->w64 : low_pool(ctx, prec);
+  void* x = W[p64 ? W_OPB : L_OPB];
+  void* t = W[p64 ? W_OPR : L_OPR];
+  void* q = W[p64 ? W_Q : L_Q];
+  const size_t n = field_elems(ctx);
+  DWA_TRY(launch_zero(ctx, prec, x, n));
+  DWA_TRY(launch_zero(ctx, prec, t, n));
+  const int Ls = ctx->Ls;
+  // the hop pair of D_bb: t = N H x ; q = G^-1 I^-1 (-1/4 H t) + x
+  const HopOp ha{x, t, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_N, 1, Ls, nullptr};
+  const HopOp hb{t, q, nullptr, x, -0.25, 0.0, 1.0, MIX_GINV_IINV, 0, Ls, nullptr};
+  auto pair = [&]() -> int {
+    DWA_TRY(launch_hop(ctx, prec, ha, nullptr));
+    return launch_hop(ctx, prec, hb, nullptr);
+  };
+  std::vector<HopTune> cands;
+  const bool spec = hop_specialised(Ls, ctx->dense_mix);
+  for (int ns : {8, 16, 32}) {
+    if (!spec && ns != 8) continue;
+    for (int ord = 0; ord < ORDER_COUNT; ++ord) {
+      if (ord == ORDER_ZDOM && ctx->dims[2] % 8 != 0) continue;  // same as SLAB there
+      HopTune c;
+      c.ns = ns;
+      c.order = ord;
+      cands.push_back(c);
+    }
+  }
+  const HopTune saved = ctx->tune[prec];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DWA_HIP(hipEventCreate(&e0), "event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(hipErrorOutOfMemory, "event");
+  }
+  int best = -1;
+  double best_us = 0.0;
+  int rc = DWA_OK;
+  std::vector<double> times(cands.size(), -1.0);
+  for (size_t k = 0; k < cands.size() && rc == DWA_OK; ++k) {
+    ctx->tune[prec] = cands[k];
+    const size_t lds = hop_mix_lds_bytes_host(cands[k].ns, Ls, p64 ? 16 : 8);
+    if (std::max(lds, ctx->hop_min_lds) > ctx->max_lds) continue;  // cannot run here
+    if ((rc = pair()) != DWA_OK || (rc = pair()) != DWA_OK) break;  // warm-up
+    if ((rc = hip_fail(hipEventRecord(e0, ctx->stream), "event record"))) break;
+    for (int r = 0; r < reps && rc == DWA_OK; ++r) rc = pair();
+    if (rc != DWA_OK) break;
+    if ((rc = hip_fail(hipEventRecord(e1, ctx->stream), "event record"))) break;
+    if ((rc = hip_fail(hipEventSynchronize(e1), "event sync"))) break;
+    float ms = 0.0f;
+    if ((rc = hip_fail(hipEventElapsedTime(&ms, e0, e1), "event time"))) break;
+    times[k] = double(ms) * 1e3 / reps;
+    if (best < 0 || times[k] < best_us) {
+      best = int(k);
+      best_us = times[k];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tune[prec] = (rc == DWA_OK && best >= 0) ? cands[best] : saved;
+  if (rc != DWA_OK) return rc;
+  if (entries)
+    for (size_t k = 0; k < cands.size() && int(k) < max_entries; ++k)
+      entries[k] = dwa_tune_entry{prec, cands[k].ns, cands[k].order, times[k]};
+  if (n_entries) *n_entries = int(cands.size());
+  return DWA_OK;
 }
 
 int dwa_apply_hop(dwa_ctx* ctx, int prec, int parity_out, int kind, void* out, const void* in) {

@@ -240,6 +240,21 @@ struct BatchWs {
 };
 }  // namespace dwa
 
+namespace dwa {
+// fused-hop tiles (sites per block) and block traversal orders
+constexpr int kTileCount = 3;
+constexpr int kTiles[kTileCount] = {8, 16, 32};
+inline int tile_index(int ns) { return ns == 8 ? 0 : (ns == 16 ? 1 : 2); }
+inline bool valid_tile(int ns) { return ns == 8 || ns == 16 || ns == 32; }
+// SLAB: (t-slab, z, t in slab, y, x), each XCD a run of it; LEX: checkerboard order;
+// ZDOM: XCD k owns z-planes [k Lz/8, (k+1) Lz/8), walked t-major.
+enum HopOrder { ORDER_SLAB = 0, ORDER_LEX = 1, ORDER_ZDOM = 2, ORDER_COUNT = 3 };
+struct HopTune {
+  int ns = 16;
+  int order = ORDER_SLAB;
+};
+}  // namespace dwa
+
 struct dwa_ctx {
   int dims[4];
   int Ls;
@@ -254,7 +269,10 @@ struct dwa_ctx {
   // geometry
   int* d_nbr = nullptr;   // [2][8][Vh] neighbour cb index for an output site of parity p
   int* d_cb2lex = nullptr;  // [2][Vh]
-  int* d_blkmap[3] = {nullptr, nullptr, nullptr};  // fused-hop block -> chunk of 8/16/32 sites
+  // fused-hop block -> chunk of sites, one table per traversal order and tile size
+  int* d_blkmap[dwa::ORDER_COUNT][dwa::kTileCount] = {};
+  dwa::HopTune tune[3];            // per storage precision (autotuner or default)
+  size_t max_lds = 64 * 1024;      // device limit on one block's LDS
   // s-matrices (FP64 and FP32 copies), [MIX_COUNT][2][Ls][Ls]
   double* d_mix64 = nullptr;
   float* d_mix32 = nullptr;
@@ -282,15 +300,15 @@ struct dwa_ctx {
 
 namespace dwa {
 
-// Sites per block of the fused hop: Ls values with their own kernels run 32 sites
-// (FP32 / BF16: one 128-byte line per colour-spin component and slice) or 16 (FP64,
-// whose LDS tile is twice as large); the generic and dense kernels run 8.
-inline int hop_sites_per_block(int prec, int Ls, bool dense) {
-  if (dense || !(Ls == 4 || Ls == 8 || Ls == 12 || Ls == 16)) return 8;
-  return prec == DWA_F64 ? 16 : 32;
+// Sites per block of the fused hop.  The Ls values with their own kernels (4, 8, 12, 16)
+// are compiled for tiles of 8, 16 and 32 sites, and the context's tuning picks one per
+// storage precision; the generic (any other Ls) and dense kernels always run 8.
+inline bool hop_specialised(int Ls, bool dense) {
+  return !dense && (Ls == 4 || Ls == 8 || Ls == 12 || Ls == 16);
 }
-// index of the block traversal table for a given number of sites per block
-inline int blkmap_index(int ns) { return ns == 8 ? 0 : (ns == 16 ? 1 : 2); }
+inline int hop_sites_per_block(const dwa_ctx* ctx, int prec) {
+  return hop_specialised(ctx->Ls, ctx->dense_mix) ? ctx->tune[prec].ns : 8;
+}
 
 // kernel launchers (kernels.hip)
 struct HopOp {

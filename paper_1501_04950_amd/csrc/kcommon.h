@@ -601,14 +601,15 @@ __device__ __forceinline__ double hop_mix_out(const HopDev& a, const lcpx<RealOf
 //            enough threads the output rows are split into groups of whole wavefronts.
 // The block order comes from a host-built table that walks each XCD's share of the
 // lattice slab by slab, keeping the neighbours' reuse distance inside one XCD's L2.
-// LS > 0: Ls is the compile-time LS; LS == 0: runtime Ls <= 32.
+// LS > 0: Ls is the compile-time LS; LS == 0: runtime Ls <= 32.  The block is NS * Ls
+// threads rounded up to whole wavefronts (the bound below matches the launcher).
 // MODE selects the epilogue at compile time so that each use is its own kernel:
 //   0: out = M H in                 (first hop of D_bb / D_bb^dag)
 //   1: out = M (hop_coef H in) + post_coef post   (second hop, with the x term; the
 //      only epilogue that also writes per-block partial sums of |out|^2)
 //   2: out = M (hop_coef H in + pre_coef pre)     (Schur prep and reconstruction)
 template <typename S, int NS, int LS, int MODE, int KIND, bool DENSE>
-__global__ void __launch_bounds__(NS*(LS > 0 ? LS : 32)) hop_mix_kernel(HopDev a0) {
+__global__ void __launch_bounds__((NS * (LS > 0 ? LS : 32) + 63) / 64 * 64) hop_mix_kernel(HopDev a0) {
   using R = RealOf<S>;
   using E = typename S::elem;
   // field rhs of a batch = blockIdx.y; chunk of sites from the XCD-aware block order.
@@ -994,8 +995,8 @@ MixTables mix_tables(dwa_ctx* ctx, int kind) {
   return T;
 }
 
-// Ls values with their own compiled kernels; any other Ls <= 32 runs the generic one,
-// which is also the only one compiled with the dense fallback.
+// Ls values with their own compiled site-local kernels; any other Ls <= 32 runs the
+// generic one, which is also the only one compiled with the dense fallback.
 #define DWA_LS_DISPATCH(Ls, dense, M) \
   if (dense) {                        \
     M(0, true);                       \
@@ -1009,17 +1010,12 @@ MixTables mix_tables(dwa_ctx* ctx, int kind) {
     }                                 \
   }
 
-template <typename S, int MODE, int KIND>
-void launch_hop_mix_mk(dwa_ctx* ctx, const HopDev& a, dim3 grid, dim3 block, size_t shm) {
-#define DWA_HOPMIX(LSV, DV)                                                                   \
-  {                                                                                           \
-    constexpr int NSV = LSV > 0 ? (S::prec == DWA_F64 ? 16 : 32) : 8;                         \
-    hipLaunchKernelGGL((hop_mix_kernel<S, NSV, LSV, MODE, KIND, DV>), grid, block, shm,       \
-                       ctx->stream, a);                                                       \
-  }
-  DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_HOPMIX)
-#undef DWA_HOPMIX
-}
+// The fused hop for one tile size (sites per block).  Defined in khop.h and compiled in
+// one translation unit per precision and tile, so that the tile variants build in
+// parallel; mode is the epilogue (0, 1, 2) and mix the output matrix kind.
+template <typename S, int NS>
+int launch_hop_tile(dwa_ctx* ctx, const HopDev& a, int mode, int mix, dim3 grid, dim3 block,
+                    size_t shm);
 
 template <typename S>
 int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
@@ -1032,8 +1028,8 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
   a.nbr = ctx->d_nbr;
   a.mix = mix_tables<S>(ctx, op.mix);
   a.partials = op.partials;
-  const int NS = hop_sites_per_block(S::prec, op.nslices, ctx->dense_mix);
-  a.blkmap = ctx->d_blkmap[blkmap_index(NS)];
+  const int NS = hop_sites_per_block(ctx, S::prec);
+  a.blkmap = ctx->d_blkmap[ctx->tune[S::prec].order][tile_index(NS)];
   a.hop_coef = op.hop_coef;
   a.pre_coef = op.pre_coef;
   a.post_coef = op.post_coef;
@@ -1075,18 +1071,18 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
     set_error("fused hop: output norms are computed only with a post term");
     return DWA_EINVAL;
   }
-  if (mode == 0 && op.mix == MIX_N) launch_hop_mix_mk<S, 0, MIX_N>(ctx, a, grid, block, shm);
-  else if (mode == 0 && op.mix == MIX_NT) launch_hop_mix_mk<S, 0, MIX_NT>(ctx, a, grid, block, shm);
-  else if (mode == 0 && op.mix == MIX_GINV_IINV) launch_hop_mix_mk<S, 0, MIX_GINV_IINV>(ctx, a, grid, block, shm);
-  else if (mode == 0 && op.mix == MIX_G_BT_G5) launch_hop_mix_mk<S, 0, MIX_G_BT_G5>(ctx, a, grid, block, shm);
-  else if (mode == 1 && op.mix == MIX_GINV_IINV) launch_hop_mix_mk<S, 1, MIX_GINV_IINV>(ctx, a, grid, block, shm);
-  else if (mode == 1 && op.mix == MIX_G_BT_G5) launch_hop_mix_mk<S, 1, MIX_G_BT_G5>(ctx, a, grid, block, shm);
-  else if (mode == 2 && op.mix == MIX_GINV_IINV && S::prec == DWA_F64)
-    launch_hop_mix_mk<S, 2, MIX_GINV_IINV>(ctx, a, grid, block, shm);
-  else {
-    set_error("fused hop: unsupported combination of output matrix and epilogue");
+  if (shm > ctx->max_lds) {
+    set_error("fused hop: the tile's LDS exceeds the device limit (choose a smaller tile)");
     return DWA_EINVAL;
   }
+  int rc = DWA_EINVAL;
+  switch (NS) {
+    case 8: rc = launch_hop_tile<S, 8>(ctx, a, mode, op.mix, grid, block, shm); break;
+    case 16: rc = launch_hop_tile<S, 16>(ctx, a, mode, op.mix, grid, block, shm); break;
+    case 32: rc = launch_hop_tile<S, 32>(ctx, a, mode, op.mix, grid, block, shm); break;
+    default: set_error("fused hop: no kernels for this tile size");
+  }
+  if (rc != DWA_OK) return rc;
   if (nblocks_out) *nblocks_out = (int)chunks;  // per field of the batch
   return hip_fail(hipGetLastError(), "hop kernel launch");
 }

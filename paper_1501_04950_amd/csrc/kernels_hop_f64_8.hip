@@ -1,0 +1,4 @@
+// gfx950 fused hop kernels of libdwa: F64 storage, 8 sites per block.
+#include "khop.h"
+
+DWA_INSTANTIATE_HOP_TILE(F64, 8)

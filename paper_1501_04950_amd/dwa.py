@@ -62,6 +62,13 @@ class DwaError(RuntimeError):
         self.status = status
 
 
+class dwa_tune_entry(ctypes.Structure):
+    _fields_ = [("prec", c_int), ("ns", c_int), ("order", c_int), ("us", c_double)]
+
+
+# block traversal orders of the fused hop (dwa_set_tuning)
+HOP_ORDERS = {"slab": 0, "lex": 1, "zdom": 2}
+
 _lib = None
 
 
@@ -101,6 +108,9 @@ def lib():
         "dwa_propagator_multi": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int), POINTER(c_void_p),
                                          POINTER(c_void_p), POINTER(dwa_solve_opts),
                                          POINTER(dwa_solve_stats)]),
+        "dwa_autotune": (c_int, [P, c_int, c_int, POINTER(dwa_tune_entry), c_int, POINTER(c_int)]),
+        "dwa_set_tuning": (c_int, [P, c_int, c_int, c_int]),
+        "dwa_get_tuning": (c_int, [P, c_int, POINTER(c_int), POINTER(c_int)]),
         "dwa_strerror": (ctypes.c_char_p, [c_int]),
         "dwa_last_error": (ctypes.c_char_p, []),
         "dwa_debug_smatrix": (c_int, [POINTER(dwa_params), c_int, POINTER(c_double)]),
@@ -265,6 +275,32 @@ class Context:
         k = MIX_KINDS[kind] if isinstance(kind, str) else int(kind)
         check(lib().dwa_apply_hop(self._h, p, int(parity_out), k, _ptr(out), _ptr(inp)))
         return out
+
+    # -- tuning ---------------------------------------------------------------
+    def autotune(self, prec="f64", reps=10):
+        """Time every tile / traversal of the fused hop for one storage precision and
+        keep the fastest (dwa_autotune).  Returns {"ns", "order", "us", "candidates"}."""
+        p = PREC[prec] if isinstance(prec, str) else int(prec)
+        ent = (dwa_tune_entry * 16)()
+        n = c_int(0)
+        check(lib().dwa_autotune(self._h, p, int(reps), ent, 16, byref(n)))
+        names = {v: k for k, v in HOP_ORDERS.items()}
+        cands = [{"ns": ent[i].ns, "order": names[ent[i].order], "us": ent[i].us}
+                 for i in range(n.value)]
+        ns, order = self.get_tuning(prec)
+        us = min((c["us"] for c in cands if c["ns"] == ns and c["order"] == order), default=None)
+        return {"ns": ns, "order": order, "us": us, "candidates": cands}
+
+    def set_tuning(self, prec, ns, order="slab"):
+        p = PREC[prec] if isinstance(prec, str) else int(prec)
+        o = HOP_ORDERS[order] if isinstance(order, str) else int(order)
+        check(lib().dwa_set_tuning(self._h, p, int(ns), o))
+
+    def get_tuning(self, prec):
+        p = PREC[prec] if isinstance(prec, str) else int(prec)
+        ns, o = c_int(0), c_int(0)
+        check(lib().dwa_get_tuning(self._h, p, byref(ns), byref(o)))
+        return ns.value, {v: k for k, v in HOP_ORDERS.items()}[o.value]
 
     # -- solvers --------------------------------------------------------------
     @staticmethod

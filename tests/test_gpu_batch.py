@@ -160,3 +160,57 @@ def test_dbb_norm_epilogue_keeps_outputs(Ls, nb):
         for k in range(nb):
             assert abs(nrm[k] - ref_n[k]) <= 1e-12 * ref_n[k]
     ctx.close()
+
+
+def _dbb_pair(ctx, x, prec):
+    return ctx.apply_Dbb(x, prec), ctx.apply_Dbb_dag(x, prec)
+
+
+def _ctx_dims(dims, Ls, seed):
+    ctx = dwa.Context(dims, Ls, -1.8, 0.05, 0.8, 1.5, 0.5)
+    ctx.set_links(torch.from_numpy(synth.su3_field(dims, 0.5, seed)).to(gpu()))
+    return ctx
+
+
+@pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 8), ((8, 8, 8, 16), 12), ((4, 2, 2, 4), 5)])
+def test_autotune_configurations_agree(dims, Ls):
+    """Every tile / traversal gives bitwise the same D_bb and D_bb^dag in all three
+    precisions; the autotuner keeps the fastest it timed; set_tuning validates; a solve
+    after tuning agrees with one on the default configuration."""
+    dev = gpu()
+    ctx = _ctx_dims(dims, Ls, 17)
+    gen = torch.Generator(device=dev).manual_seed(11)
+    say(f"[gpu] autotune {dims} Ls={Ls}")
+    for prec in ("f64", "f32", "bf16"):
+        x = ctx.half_field(prec)
+        if prec == "bf16":
+            x.copy_(torch.randn(x.shape, device=dev, generator=gen).to(torch.bfloat16))
+        else:
+            x.copy_(torch.randn(x.shape, dtype=x.dtype, device=dev, generator=gen))
+        ref = _dbb_pair(ctx, x, prec)
+        res = ctx.autotune(prec, reps=3)
+        timed = [c for c in res["candidates"] if c["us"] >= 0]
+        say(f"    {prec}: chose ns={res['ns']} {res['order']} ({res['us']:.1f} us of "
+            + ", ".join(f"{c['ns']}/{c['order']} {c['us']:.1f}" for c in timed) + ")")
+        assert timed and res["us"] == min(c["us"] for c in timed)
+        for c in timed:
+            ctx.set_tuning(prec, c["ns"], c["order"])
+            got = _dbb_pair(ctx, x, prec)
+            assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), (prec, c)
+        ctx.set_tuning(prec, res["ns"], res["order"])
+        if Ls not in (4, 8, 12, 16):
+            assert {c["ns"] for c in res["candidates"]} == {8}
+            with pytest.raises(dwa.DwaError):
+                ctx.set_tuning(prec, 16, "slab")
+    with pytest.raises(dwa.DwaError):
+        ctx.set_tuning("f64", 24, "slab")
+    with pytest.raises(dwa.DwaError):
+        ctx.set_tuning("f64", 8, 3)
+    eta = torch.from_numpy(synth.gaussian_source(dims, 3)).to(dev)
+    y1, st, rc = ctx.propagator(eta, tol=1e-12, check_every=1)
+    ctx2 = _ctx_dims(dims, Ls, 17)
+    y0, st0, rc0 = ctx2.propagator(eta, tol=1e-12, check_every=1)
+    assert rc == rc0 == dwa.DWA_OK
+    assert rel(y1, y0) < 1e-10
+    ctx.close()
+    ctx2.close()
