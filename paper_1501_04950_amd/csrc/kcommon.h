@@ -564,6 +564,17 @@ __device__ __forceinline__ double hop_mix_out(const HopDev& a, const lcpx<RealOf
   constexpr int NSP = NS + 1;
   const int sl = lt % NS, comp = CH * 6 + lt / NS;
   const unsigned site = site0 + sl;
+  // the x term first, so its loads are in flight during the LDS reads and the mix
+  cpx<R> pv[MODE == 1 ? LSM : 1];
+  if constexpr (MODE == 1) {
+    const unsigned sstride = 12u * a.Vh * unsigned(sizeof(E));
+    const __amdgpu_buffer_rsrc_t rpost = make_rsrc(a.post, unsigned(Ls) * sstride);
+    const unsigned off = (unsigned(comp) * a.Vh + site) * unsigned(sizeof(E));
+    const bool ok = site < a.Vh;
+#pragma unroll
+    for (int i = 0; i < LSM; ++i)
+      if (i < Ls) pv[i] = ok ? ldbuf<S>(rpost, off, unsigned(i) * sstride) : cmk<R>(0, 0);
+  }
   cpx<R> v[LSM];
 #pragma unroll
   for (int j = 0; j < LSM; ++j)
@@ -580,7 +591,7 @@ __device__ __forceinline__ double hop_mix_out(const HopDev& a, const lcpx<RealOf
     for (int i = 0; i < LSM; ++i)
       if (i < Ls) {
         cpx<R> o = v[i];
-        if (MODE == 1) o = o + qc * ldbuf<S>(make_rsrc(a.post, fbytes), off, unsigned(i) * sstride);
+        if constexpr (MODE == 1) o = o + qc * pv[i];
         stbuf<S>(rout, off, unsigned(i) * sstride, o);
         if constexpr (MODE == 1) nrm += (double)norm2(o);
       }
