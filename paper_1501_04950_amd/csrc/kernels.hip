@@ -38,8 +38,22 @@ __device__ __forceinline__ void block_sum_to(double v, double* out_slot) {
 }
 
 __device__ double sum_partials_block(const double* part, int n) {
+  // Thread k adds part[k], part[k + 256], ... in that order.  The loads of a group of
+  // 8 are independent and go out together: the partials were just written by blocks on
+  // every XCD, so each is a round trip to the Infinity Cache or HBM, and a loop that
+  // waited for each in turn spent most of the kernel on them.
+  constexpr int U = 8;
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  for (int base = 0; base < n; base += U * blockDim.x) {
+    double t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * int(blockDim.x) + int(threadIdx.x);
+      t[u] = i < n ? part[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v += t[u];
+  }
   __shared__ double res;
   block_sum_to(v, &res);
   __syncthreads();
