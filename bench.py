@@ -88,7 +88,7 @@ def main():
     tuning = {}
     for prec in ("f64", "f32", "bf16"):
         if args.no_tune:
-            ns, order = ctx.get_tuning(prec)
+            ns, order, _ = ctx.get_tuning(prec)
             tuning[prec] = {"ns": ns, "order": order, "tuned": False}
             continue
         t0 = time.perf_counter()
@@ -306,6 +306,9 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
         ctx = dwa.Context(dims, Ls, bw["M5"], bw["m"], bw["alpha"], bw["b"], bw["c"])
         ctx.set_links(torch.from_numpy(synth.su3_field(dims, bw["spread"], bw["seed"] + k)).to(dev))
         ctx.reserve_batch(12)
+        if not args.no_tune:
+            for prec in ("f64", "f32"):
+                ctx.autotune(prec, reps=5)
         eta = torch.from_numpy(np.stack([synth.point_source(dims, 0, j // 3, j % 3)
                                          for j in range(12)])).to(dev)
         batches.append((ctx, eta))
@@ -353,6 +356,16 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
     end.record(stream)
     end.synchronize()
     batch_ms = start.elapsed_time(end) / 5
+    ns, order, nf = ctx.get_tuning("f32")
+    ctx.set_tuning("f32", ns, order, 1)
+    ctx.apply_Dbb_batch(x, "f32", out=out)
+    start.record(stream)
+    for _ in range(5):
+        ctx.apply_Dbb_batch(x, "f32", out=out)
+    end.record(stream)
+    end.synchronize()
+    batch_nf1_ms = start.elapsed_time(end) / 5
+    ctx.set_tuning("f32", ns, order, nf)
     start.record(stream)
     for _ in range(5):
         for j in range(12):
@@ -363,9 +376,11 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
     Vh = ctx.Vh
     S = ctx.Ls * 12 * Vh * 8
     Lb = 4 * 2 * Vh * 9 * 8
-    dbb = {"fields": 12, "batched_ms": round(batch_ms, 3), "single_x12_ms": round(single_ms, 3),
+    dbb = {"fields": 12, "fields_per_block": nf, "batched_ms": round(batch_ms, 3),
+           "batched_one_field_per_block_ms": round(batch_nf1_ms, 3), "single_x12_ms": round(single_ms, 3),
            "batched_gbs_per_field_model": round(12 * (5 * S + 2 * Lb) / batch_ms / 1e6, 1)}
-    log(f"  D_bb x12 FP32 16^3x32: batched {batch_ms:.3f} ms, 12 single {single_ms:.3f} ms")
+    log(f"  D_bb x12 FP32 16^3x32: batched {batch_ms:.3f} ms ({nf} fields per block; 1: "
+        f"{batch_nf1_ms:.3f} ms), 12 single {single_ms:.3f} ms")
     for c, _ in batches:
         c.close()
     return {"workload": "8^4/Ls8 + 12^3x24/Ls12 + 16^3x32/Ls16, 12 point sources each, "

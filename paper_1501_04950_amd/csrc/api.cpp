@@ -53,11 +53,13 @@ int einval(const std::string& msg) {
   } while (0)
 #define DWA_HIP(expr, what) DWA_TRY(hip_fail((expr), what))
 
-// LDS bytes of one fused-hop block (the device code's hop_mix_lds_bytes): the larger of
-// the [Ls][12][ns+1] output tile and the [72][ns] link area, plus [8][ns] neighbours;
-// cbytes is the size of one complex in the kernel's arithmetic (16 FP64, 8 otherwise).
-size_t hop_mix_lds_bytes_host(int ns, int Ls, size_t cbytes) {
-  return std::max(size_t(Ls) * 12 * (ns + 1) * cbytes, size_t(72) * ns * cbytes) + size_t(8) * ns * 4;
+// LDS bytes of one fused-hop block (the device code's hop_mix_lds_bytes): the
+// [Ls][12][ns+1] output tile and the [72][ns] link area (sharing space when the block
+// does one field, nf = 1), plus [8][ns] neighbours; cbytes is the size of one complex
+// in the kernel's arithmetic (16 FP64, 8 otherwise).
+size_t hop_mix_lds_bytes_host(int ns, int Ls, size_t cbytes, int nf = 1) {
+  const size_t tile = size_t(Ls) * 12 * (ns + 1) * cbytes, link = size_t(72) * ns * cbytes;
+  return (nf > 1 ? tile + link : std::max(tile, link)) + size_t(8) * ns * 4;
 }
 
 void** low_pool(dwa_ctx* ctx, int prec) {
@@ -1119,25 +1121,28 @@ int dwa_apply_Dbb_dag(dwa_ctx* ctx, int prec, void* out, const void* in) {
   return apply_dbbdag(ctx, prec, out, in, W[p64 ? W_OPB : L_OPB], W[p64 ? W_OPR : L_OPR]);
 }
 
-int dwa_set_tuning(dwa_ctx* ctx, int prec, int ns, int order) {
+int dwa_set_tuning(dwa_ctx* ctx, int prec, int ns, int order, int nf) {
   DWA_TRY(check_ctx(ctx));
   if (!valid_prec(prec)) return einval("bad precision");
   if (!valid_tile(ns)) return einval("tile must be 8, 16 or 32 sites");
   if (order < 0 || order >= ORDER_COUNT) return einval("order must be 0, 1 or 2");
+  if (nf < 1 || nf > 64) return einval("fields per block must be in [1, 64]");
   if (!hop_specialised(ctx->Ls, ctx->dense_mix) && ns != 8)
     return einval("the generic hop kernel (this Ls) runs 8 sites per block");
-  const size_t lds = prec == DWA_F64 ? hop_mix_lds_bytes_host(ns, ctx->Ls, 16) : hop_mix_lds_bytes_host(ns, ctx->Ls, 8);
+  const size_t lds = hop_mix_lds_bytes_host(ns, ctx->Ls, prec == DWA_F64 ? 16 : 8, nf);
   if (std::max(lds, ctx->hop_min_lds) > ctx->max_lds) return einval("tile's LDS exceeds the device limit");
   ctx->tune[prec].ns = ns;
   ctx->tune[prec].order = order;
+  ctx->tune[prec].nf = nf;
   return DWA_OK;
 }
 
-int dwa_get_tuning(const dwa_ctx* ctx, int prec, int* ns, int* order) {
+int dwa_get_tuning(const dwa_ctx* ctx, int prec, int* ns, int* order, int* nf) {
   if (!ctx) return einval("null context");
   if (!valid_prec(prec)) return einval("bad precision");
   if (ns) *ns = hop_specialised(ctx->Ls, ctx->dense_mix) ? ctx->tune[prec].ns : 8;
   if (order) *order = ctx->tune[prec].order;
+  if (nf) *nf = ctx->tune[prec].nf;
   return DWA_OK;
 }
 
@@ -1152,69 +1157,100 @@ int dwa_autotune(dwa_ctx* ctx, int prec, int reps, dwa_tune_entry* entries, int 
   if (n_entries) *n_entries = 0;
   if (reps <= 0) reps = 10;
   const bool p64 = prec == DWA_F64;
-  void** W = p64 ? ctx->w64 : low_pool(ctx, prec);
-  void* x = W[p64 ? W_OPB : L_OPB];
-  void* t = W[p64 ? W_OPR : L_OPR];
-  void* q = W[p64 ? W_Q : L_Q];
-  const size_t n = field_elems(ctx);
-  DWA_TRY(launch_zero(ctx, prec, x, n));
-  DWA_TRY(launch_zero(ctx, prec, t, n));
   const int Ls = ctx->Ls;
-  // the hop pair of D_bb: t = N H x ; q = G^-1 I^-1 (-1/4 H t) + x
-  const HopOp ha{x, t, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_N, 1, Ls, nullptr};
-  const HopOp hb{t, q, nullptr, x, -0.25, 0.0, 1.0, MIX_GINV_IINV, 0, Ls, nullptr};
-  auto pair = [&]() -> int {
-    DWA_TRY(launch_hop(ctx, prec, ha, nullptr));
-    return launch_hop(ctx, prec, hb, nullptr);
+  const size_t n = field_elems(ctx);
+  // one timed configuration: the hop pair of D_bb, t = N H x ; q = G^-1 I^-1 (-1/4 H t) + x,
+  // on nr fields back to back
+  struct Cand {
+    HopTune t;
+    int nrhs;
+    double us;
   };
-  std::vector<HopTune> cands;
+  std::vector<Cand> cands;
   const bool spec = hop_specialised(Ls, ctx->dense_mix);
+  const HopTune saved = ctx->tune[prec];
   for (int ns : {8, 16, 32}) {
     if (!spec && ns != 8) continue;
     for (int ord = 0; ord < ORDER_COUNT; ++ord) {
       if (ord == ORDER_ZDOM && ctx->dims[2] % 8 != 0) continue;  // same as SLAB there
-      HopTune c;
+      HopTune c = saved;
       c.ns = ns;
       c.order = ord;
-      cands.push_back(c);
+      cands.push_back(Cand{c, 1, -1.0});
     }
   }
-  const HopTune saved = ctx->tune[prec];
   hipEvent_t e0 = nullptr, e1 = nullptr;
   DWA_HIP(hipEventCreate(&e0), "event");
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return hip_fail(hipErrorOutOfMemory, "event");
   }
-  int best = -1;
-  double best_us = 0.0;
-  int rc = DWA_OK;
-  std::vector<double> times(cands.size(), -1.0);
-  for (size_t k = 0; k < cands.size() && rc == DWA_OK; ++k) {
-    ctx->tune[prec] = cands[k];
-    const size_t lds = hop_mix_lds_bytes_host(cands[k].ns, Ls, p64 ? 16 : 8);
-    if (std::max(lds, ctx->hop_min_lds) > ctx->max_lds) continue;  // cannot run here
-    if ((rc = pair()) != DWA_OK || (rc = pair()) != DWA_OK) break;  // warm-up
-    if ((rc = hip_fail(hipEventRecord(e0, ctx->stream), "event record"))) break;
-    for (int r = 0; r < reps && rc == DWA_OK; ++r) rc = pair();
-    if (rc != DWA_OK) break;
-    if ((rc = hip_fail(hipEventRecord(e1, ctx->stream), "event record"))) break;
-    if ((rc = hip_fail(hipEventSynchronize(e1), "event sync"))) break;
+  auto time_pair = [&](Cand& c, void* x, void* t, void* q) -> int {
+    ctx->tune[prec] = c.t;
+    const size_t lds = hop_mix_lds_bytes_host(c.t.ns, Ls, p64 ? 16 : 8, c.nrhs > 1 ? c.t.nf : 1);
+    if (std::max(lds, ctx->hop_min_lds) > ctx->max_lds) return DWA_OK;  // cannot run here
+    const HopOp ha{x, t, nullptr, nullptr, 1.0, 0.0, 0.0, MIX_N, 1, Ls, nullptr, c.nrhs};
+    const HopOp hb{t, q, nullptr, x, -0.25, 0.0, 1.0, MIX_GINV_IINV, 0, Ls, nullptr, c.nrhs};
+    auto pair = [&]() -> int {
+      DWA_TRY(launch_hop(ctx, prec, ha, nullptr));
+      return launch_hop(ctx, prec, hb, nullptr);
+    };
+    DWA_TRY(pair());
+    DWA_TRY(pair());  // warm-up
+    DWA_HIP(hipEventRecord(e0, ctx->stream), "event record");
+    for (int r = 0; r < reps; ++r) DWA_TRY(pair());
+    DWA_HIP(hipEventRecord(e1, ctx->stream), "event record");
+    DWA_HIP(hipEventSynchronize(e1), "event sync");
     float ms = 0.0f;
-    if ((rc = hip_fail(hipEventElapsedTime(&ms, e0, e1), "event time"))) break;
-    times[k] = double(ms) * 1e3 / reps;
-    if (best < 0 || times[k] < best_us) {
-      best = int(k);
-      best_us = times[k];
+    DWA_HIP(hipEventElapsedTime(&ms, e0, e1), "event time");
+    c.us = double(ms) * 1e3 / reps;
+    return DWA_OK;
+  };
+  auto best_of = [&](size_t from) {
+    long long b = -1;
+    for (size_t k = from; k < cands.size(); ++k)
+      if (cands[k].us >= 0 && (b < 0 || cands[k].us < cands[size_t(b)].us)) b = (long long)k;
+    return b;
+  };
+  int rc = DWA_OK;
+  // tile and order, on the context's single-field workspace
+  {
+    void** W = p64 ? ctx->w64 : low_pool(ctx, prec);
+    void* x = W[p64 ? W_OPB : L_OPB];
+    void* t = W[p64 ? W_OPR : L_OPR];
+    void* q = W[p64 ? W_Q : L_Q];
+    if ((rc = launch_zero(ctx, prec, x, n)) == DWA_OK) rc = launch_zero(ctx, prec, t, n);
+    for (size_t k = 0; k < cands.size() && rc == DWA_OK; ++k) rc = time_pair(cands[k], x, t, q);
+  }
+  long long best = rc == DWA_OK ? best_of(0) : -1;
+  HopTune chosen = best >= 0 ? cands[size_t(best)].t : saved;
+  // fields per block, on a batch of up to 12 fields when one is reserved
+  const int nb = std::min(ctx->batch.nmax, 12);
+  if (rc == DWA_OK && best >= 0 && nb >= 2) {
+    BatchWs& w = ctx->batch;
+    void* x = p64 ? w.f64[B_OPB] : w.lo[prec][BL_W];
+    void* t = p64 ? w.f64[B_OPR] : w.lo[prec][BL_T];
+    void* q = p64 ? w.f64[B_Q] : w.lo[prec][BL_Q];
+    if ((rc = launch_zero(ctx, prec, x, n, nb)) == DWA_OK) rc = launch_zero(ctx, prec, t, n, nb);
+    const size_t from = cands.size();
+    for (int nf : {1, 2, 3, 4, 6, 12}) {
+      if (nf > nb) continue;
+      HopTune c = chosen;
+      c.nf = nf;
+      cands.push_back(Cand{c, nb, -1.0});
     }
+    for (size_t k = from; k < cands.size() && rc == DWA_OK; ++k) rc = time_pair(cands[k], x, t, q);
+    const long long bb = rc == DWA_OK ? best_of(from) : -1;
+    if (bb >= 0) chosen.nf = cands[size_t(bb)].t.nf;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  ctx->tune[prec] = (rc == DWA_OK && best >= 0) ? cands[best] : saved;
+  ctx->tune[prec] = (rc == DWA_OK && best >= 0) ? chosen : saved;
   if (rc != DWA_OK) return rc;
   if (entries)
     for (size_t k = 0; k < cands.size() && int(k) < max_entries; ++k)
-      entries[k] = dwa_tune_entry{prec, cands[k].ns, cands[k].order, times[k]};
+      entries[k] = dwa_tune_entry{prec, cands[k].t.ns, cands[k].t.order, cands[k].t.nf, cands[k].nrhs,
+                                  cands[k].us};
   if (n_entries) *n_entries = int(cands.size());
   return DWA_OK;
 }

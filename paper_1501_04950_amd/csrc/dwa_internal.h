@@ -252,6 +252,7 @@ enum HopOrder { ORDER_SLAB = 0, ORDER_LEX = 1, ORDER_ZDOM = 2, ORDER_COUNT = 3 }
 struct HopTune {
   int ns = 16;
   int order = ORDER_SLAB;
+  int nf = 1;  // fields per block when a batch is applied
 };
 }  // namespace dwa
 

@@ -411,6 +411,7 @@ struct HopDev {
   int nslices;
   unsigned Vh;
   unsigned nrhs;                 // fields in a batch (1 for a single field)
+  unsigned nf;                   // fields per block (the block's links serve all of them)
   unsigned long long rhs_stride; // elements from one field of the batch to the next
 };
 
@@ -547,10 +548,11 @@ __device__ __forceinline__ void hop_site_lds(__amdgpu_buffer_rsrc_t in, unsigned
 
 // LDS footprint of hop_mix_kernel in bytes.
 template <typename R>
-__host__ __device__ constexpr size_t hop_mix_lds_bytes(int NS, int Ls) {
-  return (size_t(Ls) * 12 * (NS + 1) * sizeof(cpx<R>) > size_t(72) * NS * sizeof(cpx<R>)
-              ? size_t(Ls) * 12 * (NS + 1) * sizeof(cpx<R>)
-              : size_t(72) * NS * sizeof(cpx<R>)) +
+__host__ __device__ constexpr size_t hop_mix_lds_bytes(int NS, int Ls, int nf = 1) {
+  return (nf > 1 ? size_t(Ls) * 12 * (NS + 1) * sizeof(cpx<R>) + size_t(72) * NS * sizeof(cpx<R>)
+                 : (size_t(Ls) * 12 * (NS + 1) * sizeof(cpx<R>) > size_t(72) * NS * sizeof(cpx<R>)
+                        ? size_t(Ls) * 12 * (NS + 1) * sizeof(cpx<R>)
+                        : size_t(72) * NS * sizeof(cpx<R>))) +
          size_t(8) * NS * sizeof(unsigned);
 }
 
@@ -619,29 +621,30 @@ __device__ __forceinline__ double hop_mix_out(const HopDev& a, const lcpx<RealOf
 //   1: out = M (hop_coef H in) + post_coef post   (second hop, with the x term; the
 //      only epilogue that also writes per-block partial sums of |out|^2)
 //   2: out = M (hop_coef H in + pre_coef pre)     (Schur prep and reconstruction)
-template <typename S, int NS, int LS, int MODE, int KIND, bool DENSE>
+template <typename S, int NS, int LS, int MODE, int KIND, bool DENSE, bool MULTI>
 __global__ void __launch_bounds__((NS * (LS > 0 ? LS : 32) + 63) / 64 * 64) hop_mix_kernel(HopDev a0) {
   using R = RealOf<S>;
   using E = typename S::elem;
-  // field rhs of a batch = blockIdx.y; chunk of sites from the XCD-aware block order.
-  // (No integer division by a runtime value here: its float-reciprocal expansion,
-  // rematerialised after the divergent phases, mis-indexed the partial sums.)
-  const unsigned rhs = blockIdx.y;
+  // chunk of sites from the XCD-aware block order; fields blockIdx.y * nf ... of a batch.
+  // MULTI (a0.nf > 1 fields per block) is a kernel of its own: with the field count
+  // known to be one, the single-field kernel keeps its register budget.
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
-  const HopDev a = hop_for_rhs<S>(a0, rhs);
+  const unsigned nf = MULTI ? a0.nf : 1u;
+  const HopDev a1 = hop_for_rhs<S>(a0, MULTI ? 0u : blockIdx.y);  // the field of a one-field block
   constexpr int LSM = LS > 0 ? LS : 32;
   constexpr int NSP = NS + 1;
   extern __shared__ __align__(16) char smem_raw[];
-  const int Ls = LS > 0 ? LS : a.nslices;
+  const int Ls = LS > 0 ? LS : a0.nslices;
+  // LDS: the output tile [Ls][12][NS+1]; the links [72][NS] share its space when the
+  // block does one field and follow it when the block does several (they are re-used
+  // by every field); then the neighbour offsets [8][NS].
+  const size_t tile_b = size_t(Ls) * 12 * NSP * sizeof(cpx<R>), link_b = size_t(72) * NS * sizeof(cpx<R>);
   lcpx<R>* tile = reinterpret_cast<lcpx<R>*>(smem_raw);
-  lcpx<R>* llink = tile;  // phase 0/1 only
-  const size_t region = size_t(Ls) * 12 * NSP * sizeof(cpx<R>) > size_t(72) * NS * sizeof(cpx<R>)
-                            ? size_t(Ls) * 12 * NSP * sizeof(cpx<R>)
-                            : size_t(72) * NS * sizeof(cpx<R>);
-  unsigned* lnbr = reinterpret_cast<unsigned*>(smem_raw + region);
-  const unsigned site0 = (a.blkmap ? (unsigned)a.blkmap[blk] : blk) * NS;
-  const int p = a.parity_out;
-  const unsigned Vh = a.Vh;
+  lcpx<R>* llink = reinterpret_cast<lcpx<R>*>(smem_raw + (MULTI ? tile_b : 0));
+  unsigned* lnbr = reinterpret_cast<unsigned*>(smem_raw + (MULTI ? tile_b + link_b : (tile_b > link_b ? tile_b : link_b)));
+  const unsigned site0 = (a0.blkmap ? (unsigned)a0.blkmap[blk] : blk) * NS;
+  const int p = a0.parity_out;
+  const unsigned Vh = a0.Vh;
   const unsigned cstride = Vh * unsigned(sizeof(E));  // bytes between components
 
   // phase 0: neighbour byte offsets, then links.  Thread (sl, j) stages rows j,
@@ -650,10 +653,10 @@ __global__ void __launch_bounds__((NS * (LS > 0 ? LS : 32) + 63) / 64 * 64) hop_
   const int nj = blockDim.x / NS;
   const unsigned site1 = site0 + sl1;
   for (int dir = j1; dir < 8; dir += nj)
-    lnbr[dir * NS + sl1] = site1 < Vh ? (unsigned)a.nbr[(p * 8 + dir) * Vh + site1] * unsigned(sizeof(E)) : 0u;
+    lnbr[dir * NS + sl1] = site1 < Vh ? (unsigned)a0.nbr[(p * 8 + dir) * Vh + site1] * unsigned(sizeof(E)) : 0u;
   __syncthreads();
   {
-    const E* L = (const E*)a.links;
+    const E* L = (const E*)a0.links;
     for (int r = j1; r < 72; r += nj) {
       const int dir = r / 9, k = r - 9 * dir, mu = dir & 3;
       cpx<R> v = cmk<R>(0, 0);
@@ -668,49 +671,63 @@ __global__ void __launch_bounds__((NS * (LS > 0 ? LS : 32) + 63) / 64 * 64) hop_
   }
   __syncthreads();
 
-  // phase 1: hop, thread (site sl1, slice s1)
   const int s1 = j1;
-  cpx<R> acc[12];
   const bool act1 = s1 < Ls && site1 < Vh;
-  if (act1) {
-    const unsigned sboff = unsigned(s1) * 12u * cstride;
-    hop_site_lds<S>(make_rsrc(a.in, unsigned(Ls) * 12u * cstride), sboff, cstride, lnbr, llink, sl1, NS, acc);
-    if (MODE != 0) {
-      const R hc = (R)a.hop_coef, pc = (R)a.pre_coef;
-      const unsigned off = sboff + site1 * unsigned(sizeof(E));
+  constexpr int PH = ((NS * 6 + 63) / 64) * 64;
+  // one field: hop into the tile, then the fifth-dimension mix and the stores
+  auto field = [&](const HopDev& a, unsigned rhs) {
+    // phase 1: hop, thread (site sl1, slice s1)
+    cpx<R> acc[12];
+    if (act1) {
+      const unsigned sboff = unsigned(s1) * 12u * cstride;
+      hop_site_lds<S>(make_rsrc(a.in, unsigned(Ls) * 12u * cstride), sboff, cstride, lnbr, llink, sl1, NS, acc);
+      if (MODE != 0) {
+        const R hc = (R)a.hop_coef, pc = (R)a.pre_coef;
+        const unsigned off = sboff + site1 * unsigned(sizeof(E));
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        cpx<R> o = hc * acc[k];
-        if (MODE == 2) o = o + pc * ldbuf<S>(make_rsrc(a.pre, unsigned(Ls) * 12u * cstride), off, unsigned(k) * cstride);
-        acc[k] = o;
+        for (int k = 0; k < 12; ++k) {
+          cpx<R> o = hc * acc[k];
+          if (MODE == 2) o = o + pc * ldbuf<S>(make_rsrc(a.pre, unsigned(Ls) * 12u * cstride), off, unsigned(k) * cstride);
+          acc[k] = o;
+        }
       }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = cmk<R>(0, 0);
+    }
+    // every thread is done with the links (one field: they share the tile's space) and
+    // with the previous field's tile
+    __syncthreads();
+    if (s1 < Ls) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) tile[(s1 * 12 + k) * NSP + sl1] = to_lds<R>(acc[k]);
+    }
+    __syncthreads();
+
+    // phase 2: fifth-dimension mix.  Work items are (chirality, site, component of that
+    // chirality); PH is a whole number of wavefronts and the block is launched in whole
+    // wavefronts, so the chirality is the same on every lane of a wave and the branch on
+    // it is uniform.
+    double nrm = 0.0;
+    for (int t = threadIdx.x; t < 2 * PH; t += blockDim.x) {
+      const int ch = __builtin_amdgcn_readfirstlane(t / PH), lt = t % PH;
+      if (lt >= NS * 6) continue;
+      if (ch == 0)
+        nrm += hop_mix_out<S, NS, LSM, MODE, KIND, 0, DENSE>(a, tile, site0, Ls, lt);
+      else
+        nrm += hop_mix_out<S, NS, LSM, MODE, KIND, 1, DENSE>(a, tile, site0, Ls, lt);
+    }
+    if (MODE == 1 && a.partials) block_sum_to(nrm, &a.partials[rhs * gridDim.x + blk]);
+  };
+  if constexpr (MULTI) {
+    for (unsigned f = 0; f < nf; ++f) {
+      const unsigned rhs = blockIdx.y * nf + f;
+      if (rhs >= a0.nrhs) break;  // the same for the whole block
+      field(hop_for_rhs<S>(a0, rhs), rhs);
     }
   } else {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = cmk<R>(0, 0);
+    field(a1, blockIdx.y);
   }
-  __syncthreads();  // every thread is done with the links
-  if (s1 < Ls) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) tile[(s1 * 12 + k) * NSP + sl1] = to_lds<R>(acc[k]);
-  }
-  __syncthreads();
-
-  // phase 2: fifth-dimension mix.  Work items are (chirality, site, component of that
-  // chirality); PH is a whole number of wavefronts and the block is launched in whole
-  // wavefronts, so the chirality is the same on every lane of a wave and the branch on
-  // it is uniform.
-  double nrm = 0.0;
-  constexpr int PH = ((NS * 6 + 63) / 64) * 64;
-  for (int t = threadIdx.x; t < 2 * PH; t += blockDim.x) {
-    const int ch = __builtin_amdgcn_readfirstlane(t / PH), lt = t % PH;
-    if (lt >= NS * 6) continue;
-    if (ch == 0)
-      nrm += hop_mix_out<S, NS, LSM, MODE, KIND, 0, DENSE>(a, tile, site0, Ls, lt);
-    else
-      nrm += hop_mix_out<S, NS, LSM, MODE, KIND, 1, DENSE>(a, tile, site0, Ls, lt);
-  }
-  if (MODE == 1 && a.partials) block_sum_to(nrm, &a.partials[rhs * gridDim.x + blk]);
 }
 
 // Site-local kernels run one thread per (site, colour-spin component of one chirality)
@@ -1080,6 +1097,11 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
   const unsigned nr = op.nrhs > 0 ? (unsigned)op.nrhs : 1u;
   a.nrhs = nr;
   a.rhs_stride = field_elems(ctx);
+  // fields per block of the fused hop (a batch's blocks stage their links once for nf
+  // fields)
+  const unsigned nf_t = ctx->tune[S::prec].nf > 1 ? (unsigned)ctx->tune[S::prec].nf : 1u;
+  const unsigned nf = nr > 1 ? (nf_t < nr ? nf_t : nr) : 1u;
+  a.nf = nf;
   if (op.mix == MIX_IDENTITY) {
     dim3 grid((unsigned)((ctx->Vh + 127) / 128), (unsigned)op.nslices, nr);
     hipLaunchKernelGGL(hop_plain_kernel<S>, grid, dim3(128), 0, ctx->stream, a);
@@ -1092,8 +1114,8 @@ int launch_hop_p(dwa_ctx* ctx, const HopOp& op, int* nblocks_out) {
     return DWA_EINVAL;
   }
   const unsigned chunks = (unsigned)((ctx->Vh + NS - 1) / NS);
-  const dim3 grid(chunks, nr);
-  size_t shm = hop_mix_lds_bytes<RealOf<S>>(NS, Ls);
+  const dim3 grid(chunks, (nr + nf - 1) / nf);
+  size_t shm = hop_mix_lds_bytes<RealOf<S>>(NS, Ls, int(nf));
   if (shm < ctx->hop_min_lds) shm = ctx->hop_min_lds;
   // whole wavefronts: phase 2 hands each wave one chirality, which needs the work
   // items of a wave to come from one 64-aligned range (the extra threads of the last

@@ -10,8 +10,13 @@ namespace dwa {
 // block, so only the 8-site tile carries them).
 template <typename S, int NS, int MODE, int KIND>
 int launch_hop_mix_mk(dwa_ctx* ctx, const HopDev& a, dim3 grid, dim3 block, size_t shm) {
-#define DWA_HOPMIX(LSV, DV)                                                                   \
-  hipLaunchKernelGGL((hop_mix_kernel<S, NS, LSV, MODE, KIND, DV>), grid, block, shm, ctx->stream, a)
+#define DWA_HOPMIX(LSV, DV)                                                                        \
+  do {                                                                                             \
+    if (a.nf > 1)                                                                                  \
+      hipLaunchKernelGGL((hop_mix_kernel<S, NS, LSV, MODE, KIND, DV, true>), grid, block, shm, ctx->stream, a); \
+    else                                                                                           \
+      hipLaunchKernelGGL((hop_mix_kernel<S, NS, LSV, MODE, KIND, DV, false>), grid, block, shm, ctx->stream, a); \
+  } while (0)
   if (hop_specialised(ctx->Ls, ctx->dense_mix)) {
     switch (ctx->Ls) {
       case 4: DWA_HOPMIX(4, false); break;

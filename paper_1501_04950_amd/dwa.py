@@ -63,7 +63,8 @@ class DwaError(RuntimeError):
 
 
 class dwa_tune_entry(ctypes.Structure):
-    _fields_ = [("prec", c_int), ("ns", c_int), ("order", c_int), ("us", c_double)]
+    _fields_ = [("prec", c_int), ("ns", c_int), ("order", c_int), ("nf", c_int), ("nrhs", c_int),
+                ("us", c_double)]
 
 
 # block traversal orders of the fused hop (dwa_set_tuning)
@@ -109,8 +110,8 @@ def lib():
                                          POINTER(c_void_p), POINTER(dwa_solve_opts),
                                          POINTER(dwa_solve_stats)]),
         "dwa_autotune": (c_int, [P, c_int, c_int, POINTER(dwa_tune_entry), c_int, POINTER(c_int)]),
-        "dwa_set_tuning": (c_int, [P, c_int, c_int, c_int]),
-        "dwa_get_tuning": (c_int, [P, c_int, POINTER(c_int), POINTER(c_int)]),
+        "dwa_set_tuning": (c_int, [P, c_int, c_int, c_int, c_int]),
+        "dwa_get_tuning": (c_int, [P, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
         "dwa_strerror": (ctypes.c_char_p, [c_int]),
         "dwa_last_error": (ctypes.c_char_p, []),
         "dwa_debug_smatrix": (c_int, [POINTER(dwa_params), c_int, POINTER(c_double)]),
@@ -278,29 +279,33 @@ class Context:
 
     # -- tuning ---------------------------------------------------------------
     def autotune(self, prec="f64", reps=10):
-        """Time every tile / traversal of the fused hop for one storage precision and
-        keep the fastest (dwa_autotune).  Returns {"ns", "order", "us", "candidates"}."""
+        """Time every tile / traversal of the fused hop for one storage precision (and,
+        with a batch reserved, the fields per block of the batched hop) and keep the
+        fastest (dwa_autotune).  Returns {"ns", "order", "nf", "us", "candidates"}; us is
+        the chosen tile's single-field hop-pair time."""
         p = PREC[prec] if isinstance(prec, str) else int(prec)
-        ent = (dwa_tune_entry * 16)()
+        ent = (dwa_tune_entry * 32)()
         n = c_int(0)
-        check(lib().dwa_autotune(self._h, p, int(reps), ent, 16, byref(n)))
+        check(lib().dwa_autotune(self._h, p, int(reps), ent, 32, byref(n)))
         names = {v: k for k, v in HOP_ORDERS.items()}
-        cands = [{"ns": ent[i].ns, "order": names[ent[i].order], "us": ent[i].us}
-                 for i in range(n.value)]
-        ns, order = self.get_tuning(prec)
-        us = min((c["us"] for c in cands if c["ns"] == ns and c["order"] == order), default=None)
-        return {"ns": ns, "order": order, "us": us, "candidates": cands}
+        cands = [{"ns": ent[i].ns, "order": names[ent[i].order], "nf": ent[i].nf,
+                  "nrhs": ent[i].nrhs, "us": ent[i].us} for i in range(n.value)]
+        ns, order, nf = self.get_tuning(prec)
+        us = min((c["us"] for c in cands if c["nrhs"] == 1 and c["ns"] == ns and c["order"] == order),
+                 default=None)
+        return {"ns": ns, "order": order, "nf": nf, "us": us, "candidates": cands}
 
-    def set_tuning(self, prec, ns, order="slab"):
+    def set_tuning(self, prec, ns, order="slab", nf=1):
         p = PREC[prec] if isinstance(prec, str) else int(prec)
         o = HOP_ORDERS[order] if isinstance(order, str) else int(order)
-        check(lib().dwa_set_tuning(self._h, p, int(ns), o))
+        check(lib().dwa_set_tuning(self._h, p, int(ns), o, int(nf)))
 
     def get_tuning(self, prec):
+        """(sites per block, block order, fields per block of a batched hop)."""
         p = PREC[prec] if isinstance(prec, str) else int(prec)
-        ns, o = c_int(0), c_int(0)
-        check(lib().dwa_get_tuning(self._h, p, byref(ns), byref(o)))
-        return ns.value, {v: k for k, v in HOP_ORDERS.items()}[o.value]
+        ns, o, nf = c_int(0), c_int(0), c_int(0)
+        check(lib().dwa_get_tuning(self._h, p, byref(ns), byref(o), byref(nf)))
+        return ns.value, {v: k for k, v in HOP_ORDERS.items()}[o.value], nf.value
 
     # -- solvers --------------------------------------------------------------
     @staticmethod

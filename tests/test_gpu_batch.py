@@ -214,3 +214,39 @@ def test_autotune_configurations_agree(dims, Ls):
     assert rel(y1, y0) < 1e-10
     ctx.close()
     ctx2.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_fields_per_block_agree(prec):
+    """A batched hop whose blocks apply their staged links to nf fields in turn gives,
+    for every nf, bitwise the D_bb (and |D_bb x|^2 per field) of one field per block;
+    with a batch reserved the autotuner times the fields per block too."""
+    dev = gpu()
+    dims, Ls, nb = (8, 8, 8, 16), 12, 12
+    ctx = _ctx_dims(dims, Ls, 23)
+    ctx.reserve_batch(nb)
+    gen = torch.Generator(device=dev).manual_seed(29)
+    x = torch.stack([ctx.half_field(prec) for _ in range(nb)]).contiguous()
+    if prec == "bf16":
+        x.copy_(torch.randn(x.shape, device=dev, generator=gen).to(torch.bfloat16))
+    else:
+        x.copy_(torch.randn(x.shape, dtype=x.dtype, device=dev, generator=gen))
+    ns, order, _ = ctx.get_tuning(prec)
+    ctx.set_tuning(prec, ns, order, 1)
+    ref, ref_n = ctx.apply_Dbb_batch(x, prec, norms=True)
+    for nf in (2, 3, 4, 5, 12, 16):
+        ctx.set_tuning(prec, ns, order, nf)
+        y, nrm = ctx.apply_Dbb_batch(x, prec, norms=True)
+        assert torch.equal(y, ref), nf
+        assert nrm == ref_n, nf
+    res = ctx.autotune(prec, reps=3)
+    batch = [c for c in res["candidates"] if c["nrhs"] > 1]
+    say(f"[gpu] {prec} batched hop pair: " + ", ".join(f"nf={c['nf']} {c['us']:.1f} us" for c in batch)
+        + f"; chose nf={res['nf']}")
+    assert {c["nf"] for c in batch} == {1, 2, 3, 4, 6, 12}
+    assert res["nf"] == min((c for c in batch if c["us"] >= 0), key=lambda c: c["us"])["nf"]
+    y, nrm = ctx.apply_Dbb_batch(x, prec, norms=True)
+    assert torch.equal(y, ref)
+    with pytest.raises(dwa.DwaError):
+        ctx.set_tuning(prec, ns, order, 0)
+    ctx.close()
