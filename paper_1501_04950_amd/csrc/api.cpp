@@ -1748,7 +1748,8 @@ int dwa_propagator_multi(dwa_ctx* const* ctxs, int nctx, const int* nrhs, void* 
           w.h_coef[2 * f] = fac[f];
           w.h_coef[2 * f + 1] = 0.0;
           w.h_coef[2 * nr + f] = fac[f] * fac[f];
-          w.h_coef[3 * nr + f] = 1.0 / scale[i][f];
+          // a zero source has scale 0 (frozen from the start): keep its r at 0
+          w.h_coef[3 * nr + f] = scale[i][f] > 0.0 ? 1.0 / scale[i][f] : 0.0;
         }
         DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * 4 * nr, hipMemcpyHostToDevice, st),
                 "coef upload");

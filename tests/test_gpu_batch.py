@@ -250,3 +250,21 @@ def test_fields_per_block_agree(prec):
     with pytest.raises(dwa.DwaError):
         ctx.set_tuning(prec, ns, order, 0)
     ctx.close()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_batch_with_zero_source(inner):
+    """A zero source inside a batch gives y_1 = 0 at iteration 0; the other fields solve
+    as they do alone."""
+    ctx, w = _ctx("c1_4x4x4x4_ls8", 0.8)
+    eta = torch.from_numpy(spin_colour_sources(w["dims"])[:4].copy()).to(gpu())
+    eta[2].zero_()
+    ctx.reserve_batch(4)
+    y, st, rc = ctx.propagator_batch(eta, tol=1e-10, inner_prec=inner, check_every=1)
+    assert rc == dwa.DWA_OK
+    assert st[2]["iters"] == 0 and float(torch.max(torch.abs(y[2]))) == 0.0
+    for k in (0, 1, 3):
+        ys, s1, rc1 = ctx.propagator(eta[k].contiguous(), tol=1e-10, inner_prec=inner, check_every=1)
+        assert rc1 == dwa.DWA_OK and st[k]["rel_resid"] <= 1e-10
+        assert rel(y[k], ys) < 1e-8
+    ctx.close()

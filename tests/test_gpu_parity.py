@@ -23,8 +23,10 @@ CASES = {
     "tiny_2x2x2x2_ls4": ((2, 2, 2, 2), 4, -1.8, 0.1, 0.7, None, None),
     "ragged_2x2x2x6_ls2": ((2, 2, 2, 6), 2, -1.7, 0.2, 1.3, None, None),
     "c1_4x4x4x4_ls8": ((4, 4, 4, 4), 8, -1.8, 0.05, 0.8, 1.5, 0.5),
-    "lsmax32_4x2x2x4_ls20": ((4, 2, 2, 4), 20, -1.6, 0.03, 0.9, None, None),
+    "ls20_4x2x2x4": ((4, 2, 2, 4), 20, -1.6, 0.03, 0.9, None, None),
     "odd_4x2x2x4_ls5": ((4, 2, 2, 4), 5, -1.8, 0.1, 0.8, None, None),
+    # the largest Ls the library takes (generic kernel, register arrays of 32 slices)
+    "lsmax32_2x2x2x4_ls32": ((2, 2, 2, 4), 32, -1.8, 0.05, 0.8, None, None),
     "c2_8x8x8x16_ls12": ((8, 8, 8, 16), 12, -1.8, 0.02, 0.6, 1.5, 0.5),
 }
 
@@ -338,6 +340,18 @@ def test_mixed_precision_bench_workload(inner, mode, delta):
     ctx.close()
 
 
+@pytest.mark.parametrize("inner", ["f64", "bf16"])
+def test_zero_source_gives_zero(inner):
+    """eta = 0: the solve stops at once with y_1 = 0 and status ok (degenerate case)."""
+    cs = case("c1_4x4x4x4_ls8")
+    ctx = cs.ctx()
+    eta = torch.zeros((int(np.prod(cs.dims)), 4, 3), dtype=torch.complex128, device=gpu())
+    y, st, rc = ctx.propagator(eta, tol=1e-10, inner_prec=inner)
+    assert rc == dwa.DWA_OK and st["converged"] and st["iters"] == 0
+    assert float(torch.max(torch.abs(y))) == 0.0
+    ctx.close()
+
+
 def test_error_paths():
     cs = case("tiny_2x2x2x2_ls4")
     dev = gpu()
@@ -362,7 +376,7 @@ def test_error_paths():
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["ragged_2x2x2x6_ls2", "c1_4x4x4x4_ls8", "lsmax32_4x2x2x4_ls20"])
+@pytest.mark.parametrize("name", ["ragged_2x2x2x6_ls2", "c1_4x4x4x4_ls8", "ls20_4x2x2x4"])
 @pytest.mark.parametrize("kind", ["identity", "N", "G_BT_g5"])
 def test_single_hop_launch(name, kind):
     """dwa_apply_hop: out = M_kind H_rb x_b with H the hopping sum of eq.(wilson) without
