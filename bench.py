@@ -247,7 +247,7 @@ def main():
 
     dom = kern[args.inner]
     ns_dom = tuning[args.inner]["ns"]
-    dom_name = f"dwa::hop_mix_kernel<dwa::{args.inner.upper()}, {ns_dom}, {Ls}, 0, 2, false>"
+    dom_name = f"dwa::hop_mix_kernel<dwa::{args.inner.upper()}, {ns_dom}, {Ls}, 0, 2, false, false>"
     roofline = {
         "bound": "hbm",
         "kernel": f"hop_mix_kernel<{args.inner.upper()},{ns_dom},{Ls},0> (fused Wilson hop + N mix)",
@@ -271,11 +271,13 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"{args.inner} storage, f32 arithmetic; f64 outer",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{dims[0]}^3x{dims[3]} Ls={Ls} m={w['m']} alpha={args.alpha} "
                                f"M5={w['M5']} b={w['b']} c={w['c']} Z2 source, tol {args.tol}",
-                   "plaquette": round(plaq, 6), "inner": args.inner, "delta": delta,
+                   "plaquette": round(plaq, 6), "storage": args.inner, "arithmetic": "f32",
+                   "outer": "f64 reliable updates" if args.mixed_mode == "reliable" else "f64 defect correction",
+                   "inner": args.inner, "delta": delta,
                    "mixed_mode": args.mixed_mode},
         "mixed": {"time_s": round(mixed_s, 4), "iters": stats[-1]["iters"],
                   "outer": stats[-1]["outer"], "rel_resid": stats[-1]["rel_resid"],
