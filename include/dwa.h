@@ -40,7 +40,9 @@
  *
  * Streams: all work is enqueued on the stream given to dwa_create (0 = default
  * stream).  Operator calls return without synchronising; solves synchronise on
- * their convergence checks and before returning.
+ * their convergence checks and before returning.  A context is not thread-safe: calls
+ * on one context must not overlap (they share its workspace); different contexts are
+ * independent.
  *
  * Errors: every call returns a dwa_status; nothing is thrown across the ABI.
  * Argument validation happens before any HIP call and returns DWA_EINVAL.
