@@ -268,3 +268,30 @@ def test_batch_with_zero_source(inner):
         assert rc1 == dwa.DWA_OK and st[k]["rel_resid"] <= 1e-10
         assert rel(y[k], ys) < 1e-8
     ctx.close()
+
+
+def test_graph_replay_equals_eager(monkeypatch):
+    """The batched CGNE replayed from a hipGraph (many replays, host checks and eager
+    reliable updates between them) gives bitwise the result of the same launches issued
+    one by one (DWA_BATCH_NO_GRAPH), for an FP64 and a BF16-inner batch."""
+    ctx, w = _ctx("c2_8x8x8x16_ls12", 0.8)
+    eta = torch.from_numpy(spin_colour_sources(w["dims"])[:6].copy()).to(gpu())
+    ctx.reserve_batch(6)
+    for kw in (dict(tol=1e-10, check_every=7), dict(tol=1e-10, inner_prec="bf16", delta=0.3, check_every=7)):
+        y_g, st_g, rc_g = ctx.propagator_batch(eta, **kw)
+        monkeypatch.setenv("DWA_BATCH_NO_GRAPH", "1")
+        y_e, st_e, rc_e = ctx.propagator_batch(eta, **kw)
+        monkeypatch.delenv("DWA_BATCH_NO_GRAPH")
+        say(f"[gpu] graph vs eager {kw.get('inner_prec', 'f64')}: iters {[s['iters'] for s in st_g]}")
+        assert rc_g == rc_e == dwa.DWA_OK
+        assert [s["iters"] for s in st_g] == [s["iters"] for s in st_e]
+        assert torch.equal(y_g, y_e)
+        # the same solve with 3 fields per hop block: partial sums are grouped per field
+        # and chunk either way, so the result is bitwise the same
+        prec = kw.get("inner_prec", "f64")
+        ns, order, nf0 = ctx.get_tuning(prec)
+        ctx.set_tuning(prec, ns, order, 3)
+        y_m, st_m, rc_m = ctx.propagator_batch(eta, **kw)
+        ctx.set_tuning(prec, ns, order, nf0)
+        assert rc_m == dwa.DWA_OK and torch.equal(y_m, y_g)
+    ctx.close()
