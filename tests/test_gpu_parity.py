@@ -144,6 +144,49 @@ def test_dbb_matches_oracle(name):
     ctx.close()
 
 
+def test_full_size_dbb_matches_oracle():
+    """The bench workload at its full size (16^3 x 32, L_s = 16, APE-smeared links,
+    alpha = 1) in the configuration bench.py times (autotuned tile and block order):
+    the FP64 D_bb of one seeded black field against the oracle's, element by element
+    (one oracle application, about 35 s of host time), and <y, D_bb x> =
+    <D_bb^dag y, x> for the GPU operators (FP64, and FP32 / BF16 to their rounding)."""
+    name = "c3_16x16x16x32_ls16"
+    w = synth.WORKLOADS[name]
+    dev = gpu()
+    U = synth.workload_links(name)
+    p = redblack.Params.make(w["dims"], w["Ls"], w["M5"], w["m"], 1.0, w["b"], w["c"])
+    say("[gpu] full-size D_bb: oracle set-up")
+    rb = redblack.RedBlack(U, p)
+    x = synth.gaussian_field5(w["dims"], w["Ls"], 1603) * rb.black
+    y = synth.gaussian_field5(w["dims"], w["Ls"], 1604) * rb.black
+    ctx = dwa.Context(w["dims"], w["Ls"], w["M5"], w["m"], 1.0, w["b"], w["c"])
+    ctx.set_links(torch.from_numpy(U).to(dev))
+    for prec in ("f64", "f32", "bf16"):
+        ctx.autotune(prec, reps=3)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    yt = torch.from_numpy(np.ascontiguousarray(y)).to(dev)
+    xh, yh = ctx.pack(xt, 0, "f64"), ctx.pack(yt, 0, "f64")
+    got = torch.zeros_like(xt)
+    ctx.unpack(ctx.apply_Dbb(xh, "f64"), 0, "f64", out=got)
+    say("[gpu] full-size D_bb: oracle application")
+    ref = rb.Dbb(x)
+    r = rel(got.cpu().numpy(), ref)
+    say(f"    full-size D_bb rel err {r:.2e} (tuning f64 {ctx.get_tuning('f64')})")
+    assert r < 1e-13
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-6), ("bf16", 2e-2)):
+        xp, yp = ctx.pack(xt, 0, prec), ctx.pack(yt, 0, prec)
+        lhs = torch.zeros_like(xt)
+        rhs = torch.zeros_like(xt)
+        ctx.unpack(ctx.apply_Dbb(xp, prec), 0, prec, out=lhs)
+        ctx.unpack(ctx.apply_Dbb(yp, prec, dagger=True), 0, prec, out=rhs)
+        a = complex(torch.sum(torch.conj(yt) * lhs))
+        b = complex(torch.sum(torch.conj(rhs) * xt))
+        d = abs(a - b) / abs(a)
+        say(f"    {prec}: |<y, D x> - <D^dag y, x>| / |<y, D x>| = {d:.1e}")
+        assert d < tol
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 2e-2)])
 def test_dbb_low_precision_error(prec, bound):
     cs = case("c1_4x4x4x4_ls8")
