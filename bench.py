@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--mixed-mode", default="reliable", choices=["reliable", "defect"])
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--check-every", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
     ap.add_argument("--no-sweep", action="store_true", help="skip the alpha sweep")
@@ -176,7 +176,7 @@ def main():
         log(f"  FP64: {fp64['time_s']:.3f} s, {st64['iters']} iters, resid {st64['rel_resid']:.2e}")
 
     # --- mixed-precision steps (timed) ------------------------------------------------
-    delta = args.delta if args.delta is not None else (0.3 if args.inner == "bf16" else 0.05)
+    delta = args.delta if args.delta is not None else (0.3 if args.inner == "bf16" else 0.02)
     kw = dict(tol=args.tol, inner_prec=args.inner, delta=delta, check_every=args.check_every,
               mixed_mode=args.mixed_mode)
     for i in range(args.warmup):
