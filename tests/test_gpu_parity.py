@@ -187,6 +187,36 @@ def test_full_size_dbb_matches_oracle():
     ctx.close()
 
 
+def test_full_size_propagator_solves_full_system():
+    """End to end at full size, as bench.py runs it: the BF16-inner solve (delta 0.3,
+    host check every 5, autotuned kernels) of the Z2 source on 16^3 x 32, L_s = 16
+    returns a 5D psi that satisfies the oracle's literal D_alpha psi = D_1(1) P eta
+    (eq.(mobius1), eq.(tosolve1)) to the accuracy of the 1e-10 Schur solve, and y_1 is
+    its wall projection."""
+    name = "c3_16x16x16x32_ls16"
+    w = synth.WORKLOADS[name]
+    dev = gpu()
+    U = synth.workload_links(name)
+    eta = synth.z2_source(w["dims"], w["seed"] + 100)
+    ctx = dwa.Context(w["dims"], w["Ls"], w["M5"], w["m"], 1.0, w["b"], w["c"])
+    ctx.set_links(torch.from_numpy(U).to(dev))
+    for prec in ("f64", "bf16"):
+        ctx.autotune(prec, reps=3)
+    say("[gpu] full-size BF16-inner propagator with psi")
+    y, st, rc, psi = ctx.propagator(torch.from_numpy(eta).to(dev), want_psi=True, tol=1e-10,
+                                    inner_prec="bf16", delta=0.3, check_every=5)
+    assert rc == dwa.DWA_OK and st["rel_resid"] <= 1e-10
+    psi = psi.cpu().numpy()
+    ctx.close()
+    p = redblack.Params.make(w["dims"], w["Ls"], w["M5"], w["m"], 1.0, w["b"], w["c"])
+    say("    oracle: D_alpha psi against D_1(1) P eta")
+    rho = redblack.source_rhs(U, eta, p)
+    res = rel(redblack.RedBlack(U, p).D(psi), rho)
+    say(f"    full-system relative residual {res:.2e} (Schur residual {st['rel_resid']:.2e})")
+    assert res < 1e-8
+    assert rel(y.cpu().numpy(), redblack.extract_y1(psi)) < 1e-15
+
+
 @pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 2e-2)])
 def test_dbb_low_precision_error(prec, bound):
     cs = case("c1_4x4x4x4_ls8")
