@@ -394,11 +394,12 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
     DWA_TRY(dbb_from_premix(ctx, inner, q, p, u, t, bank(ctx, 0), &nbA));
     DWA_TRY(launch_cg_finalize(ctx, 0, sc, bank(ctx, 0), nbA, nullptr, 0));
     DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB));
-    DWA_TRY(launch_cg_finalize(ctx, 4, sc, bank(ctx, 1), nbB, nullptr, 0));
     ndbb += 1;
     ++k;
     bool update = false, done = false;
     if (k % check_every == 0 || k >= o->maxiter) {
+      // |r_l|^2 for the host (only at a check: the next D_bb^dag step recomputes it)
+      DWA_TRY(launch_cg_finalize(ctx, 4, sc, bank(ctx, 1), nbB, nullptr, 0));
       DWA_TRY(read_scalars(ctx));
       const DevScalars& h = *ctx->h_scal;
       if (h.flags) {
@@ -543,6 +544,7 @@ struct BatchSys {
   std::vector<double> tol;    // per field; a field with tol < 0 starts frozen
   std::vector<int> iters, converged, breakdown;
   long long n_dbb = 0;
+  int nb_r = 0;  // partial sums of |r|^2 per field in bank 1 (set by the first half)
 };
 
 // Called at every host check (k > 0) for each system; last is set at maxiter.
@@ -571,7 +573,8 @@ int batch_freeze(BatchSys& b, int k, hipStream_t st) {
 
 // The CGLS iteration is split at the point where the host looks at the scalars, right
 // after x and r have been updated (as in the single-field reliable solver):
-//   first half:  q = A p, a = gamma / |q|^2, x += a p, r -= a q, |r|^2, w = premix of r
+//   first half:  q = A p, a = gamma / |q|^2, x += a p, r -= a q, |r|^2 partials,
+//                w = premix of r (|r|^2 itself is summed only before a host check)
 //   second half: z = A^dag r, beta = |z|^2 / gamma, p = z + beta p, u = premix of p
 // The graph body is (second half, first half); the first iteration runs its first half
 // eagerly.  A host check after k bodies therefore sees the residual of k updates of x.
@@ -582,7 +585,7 @@ int batch_first_half(BatchSys& b) {
   DWA_TRY(dbb_from_premix(ctx, b.prec, b.q, b.p, b.u, b.t, bbank(ctx, 0), &nbA, b.nr));
   DWA_TRY(launch_cg_finalize(ctx, 0, sc, bbank(ctx, 0), nbA, nullptr, 0, b.nr));
   DWA_TRY(launch_cg_update1(ctx, b.prec, b.x, b.r, b.w, b.p, b.q, sc, bbank(ctx, 1), &nbB, false, b.nr));
-  DWA_TRY(launch_cg_finalize(ctx, 4, sc, bbank(ctx, 1), nbB, nullptr, 0, b.nr));
+  b.nb_r = nbB;  // |r|^2 partials: summed into rr only before a host check
   b.n_dbb += b.nr;
   return DWA_OK;
 }
@@ -662,10 +665,18 @@ int cgls_multi(std::vector<BatchSys>& S, hipStream_t st, int maxiter, int check_
   };
   int k = 0;
   for (;;) {
-    // host check: read every system's scalars
+    // host check: |r|^2 of the last update (after the first iteration; before it the
+    // set-up's rr = |rhs|^2 stands), then every system's scalars
     int active = 0;
     for (auto& b : S) {
       BatchWs& w = b.ctx->batch;
+      if (k > 0) {
+        const int rc = launch_cg_finalize(b.ctx, 4, w.d_scal, bbank(b.ctx, 1), b.nb_r, nullptr, 0, b.nr);
+        if (rc != DWA_OK) {
+          cleanup();
+          return rc;
+        }
+      }
       const hipError_t e = hipMemcpyAsync(w.h_scal, w.d_scal, sizeof(DevScalars) * b.nr,
                                           hipMemcpyDeviceToHost, st);
       if (e != hipSuccess) {
