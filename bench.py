@@ -88,14 +88,16 @@ def main():
     tuning = {}
     for prec in ("f64", "f32", "bf16"):
         if args.no_tune:
-            ns, order, _ = ctx.get_tuning(prec)
+            ns, order, _, _ = ctx.get_tuning(prec)
             tuning[prec] = {"ns": ns, "order": order, "tuned": False}
             continue
         t0 = time.perf_counter()
         res = ctx.autotune(prec, reps=10)
-        tuning[prec] = {"ns": res["ns"], "order": res["order"], "pair_us": round(res["us"], 2),
+        tuning[prec] = {"ns": res["ns"], "order": res["order"], "dense": res["dense"],
+                        "pair_us": round(res["us"], 2),
                         "tuned": True, "tune_s": round(time.perf_counter() - t0, 3),
-                        "candidates": [[c["ns"], c["order"], round(c["us"], 2)] for c in res["candidates"]]}
+                        "candidates": [[c["ns"], c["order"], "dense" if c["dense"] else "sweep",
+                                        round(c["us"], 2)] for c in res["candidates"]]}
         log(f"autotune {prec}: ns={res['ns']} order={res['order']} pair {res['us']:.1f} us")
 
     eb = {"f64": 16, "f32": 8, "bf16": 4}
@@ -358,8 +360,8 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
     end.record(stream)
     end.synchronize()
     batch_ms = start.elapsed_time(end) / 5
-    ns, order, nf = ctx.get_tuning("f32")
-    ctx.set_tuning("f32", ns, order, 1)
+    ns, order, nf, dense = ctx.get_tuning("f32")
+    ctx.set_tuning("f32", ns, order, 1, dense)
     ctx.apply_Dbb_batch(x, "f32", out=out)
     start.record(stream)
     for _ in range(5):
@@ -367,7 +369,7 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
     end.record(stream)
     end.synchronize()
     batch_nf1_ms = start.elapsed_time(end) / 5
-    ctx.set_tuning("f32", ns, order, nf)
+    ctx.set_tuning("f32", ns, order, nf, dense)
     start.record(stream)
     for _ in range(5):
         for j in range(12):

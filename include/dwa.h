@@ -179,30 +179,39 @@ typedef struct {
   int ns;    /* sites per block */
   int order; /* block traversal */
   int nf;    /* fields per block when a batch is applied */
+  int dense; /* 1: dense L_s x L_s fifth-dimension matrices (generic 8-site kernel),
+                0: the O(L_s) sweep programs */
   int nrhs;  /* fields the configuration was timed on (1, or a batch) */
   double us; /* average time of one hop pair of D_bb (N hop, then G^-1 I^-1 hop with the
                 x term) on nrhs fields, microseconds; negative if the configuration
                 cannot run here (its LDS exceeds the device limit) */
 } dwa_tune_entry;
 
-/* Autotuner: time every tile and order of precision prec on this context's lattice
- * (reps timed pairs each after a warm-up; reps <= 0 means 10) and keep the fastest for
- * all later calls on the context.  When a batch is reserved (dwa_reserve_batch) it then
- * times, with that tile and order, 1, 2, 3, 4, 6 and 12 fields per block on a batch of
- * up to 12 fields: a block of the batched hop stages its links once and applies them
- * to nf fields in turn.  Uses the context's own workspaces (no allocation; their
- * contents are overwritten, nothing else is touched).  entries (host, may be NULL)
- * receives up to max_entries timings; *n_entries (may be NULL) the number timed. */
+/* Autotuner: time every tile and order of precision prec on this context's lattice,
+ * and the dense fifth-dimension matrices (generic 8-site kernel) against the sweep
+ * programs (reps timed pairs each after a warm-up; reps <= 0 means 10), and keep the
+ * fastest for all later calls on the context.  When a batch is reserved
+ * (dwa_reserve_batch) it then times, with that configuration, 1, 2, 3, 4, 6 and 12
+ * fields per block on a batch of up to 12 fields: a block of the batched hop stages its
+ * links once and applies them to nf fields in turn.  Uses the context's own workspaces
+ * (no allocation; their contents are overwritten, nothing else is touched).  entries
+ * (host, may be NULL) receives up to max_entries timings; *n_entries (may be NULL) the
+ * number timed. */
 int dwa_autotune(dwa_ctx *ctx, int prec, int reps, dwa_tune_entry *entries, int max_entries,
                  int *n_entries);
 
-/* Set or read the configuration used for precision prec (ns sites per block, block
- * order, nf fields per block of a batched hop; nf = 1 by default).  dwa_set_tuning
- * rejects a tile other than 8, 16, 32, an order outside 0..2, nf outside 1..64, a tile
- * other than 8 where the generic kernel runs, and a configuration whose LDS exceeds the
- * device limit (DWA_EINVAL).  Output pointers of dwa_get_tuning may be NULL. */
-int dwa_set_tuning(dwa_ctx *ctx, int prec, int ns, int order, int nf);
-int dwa_get_tuning(const dwa_ctx *ctx, int prec, int *ns, int *order, int *nf);
+/* Set or read the configuration used for precision prec: ns sites per block, block
+ * order, nf fields per block of a batched hop (1 by default), and dense = 1 for the
+ * dense fifth-dimension matrices instead of the sweep programs (0 by default; a context
+ * whose sweep programs failed their check at creation always runs dense, and
+ * dwa_get_tuning reports it).  The dense matrices run in the generic 8-site kernels of
+ * every precision-specific launch (hop, site-local mixes, CG updates).  dwa_set_tuning
+ * rejects a tile other than 8, 16, 32, an order outside 0..2, nf outside 1..64, dense
+ * other than 0 / 1, a tile other than 8 where the generic kernel runs, and a
+ * configuration whose LDS exceeds the device limit (DWA_EINVAL).  Output pointers of
+ * dwa_get_tuning may be NULL. */
+int dwa_set_tuning(dwa_ctx *ctx, int prec, int ns, int order, int nf, int dense);
+int dwa_get_tuning(const dwa_ctx *ctx, int prec, int *ns, int *order, int *nf, int *dense);
 
 /* Solve D_bb x_b = rhs_b by CG on the normal equations (Sec. 3).  x_b and rhs_b are
  * FP64 black SoA fields.  Returns DWA_OK, DWA_ENOCONV (x_b holds the last iterate) or

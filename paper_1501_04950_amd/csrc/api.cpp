@@ -1132,28 +1132,31 @@ int dwa_apply_Dbb_dag(dwa_ctx* ctx, int prec, void* out, const void* in) {
   return apply_dbbdag(ctx, prec, out, in, W[p64 ? W_OPB : L_OPB], W[p64 ? W_OPR : L_OPR]);
 }
 
-int dwa_set_tuning(dwa_ctx* ctx, int prec, int ns, int order, int nf) {
+int dwa_set_tuning(dwa_ctx* ctx, int prec, int ns, int order, int nf, int dense) {
   DWA_TRY(check_ctx(ctx));
   if (!valid_prec(prec)) return einval("bad precision");
   if (!valid_tile(ns)) return einval("tile must be 8, 16 or 32 sites");
   if (order < 0 || order >= ORDER_COUNT) return einval("order must be 0, 1 or 2");
   if (nf < 1 || nf > 64) return einval("fields per block must be in [1, 64]");
-  if (!hop_specialised(ctx->Ls, ctx->dense_mix) && ns != 8)
-    return einval("the generic hop kernel (this Ls) runs 8 sites per block");
+  if (dense != 0 && dense != 1) return einval("dense must be 0 or 1");
+  if (!hop_specialised(ctx->Ls, ctx->dense_mix || dense) && ns != 8)
+    return einval("the generic hop kernel (this Ls, or dense matrices) runs 8 sites per block");
   const size_t lds = hop_mix_lds_bytes_host(ns, ctx->Ls, prec == DWA_F64 ? 16 : 8, nf);
   if (std::max(lds, ctx->hop_min_lds) > ctx->max_lds) return einval("tile's LDS exceeds the device limit");
   ctx->tune[prec].ns = ns;
   ctx->tune[prec].order = order;
   ctx->tune[prec].nf = nf;
+  ctx->tune[prec].dense = dense != 0;
   return DWA_OK;
 }
 
-int dwa_get_tuning(const dwa_ctx* ctx, int prec, int* ns, int* order, int* nf) {
+int dwa_get_tuning(const dwa_ctx* ctx, int prec, int* ns, int* order, int* nf, int* dense) {
   if (!ctx) return einval("null context");
   if (!valid_prec(prec)) return einval("bad precision");
-  if (ns) *ns = hop_specialised(ctx->Ls, ctx->dense_mix) ? ctx->tune[prec].ns : 8;
+  if (ns) *ns = hop_sites_per_block(ctx, prec);
   if (order) *order = ctx->tune[prec].order;
   if (nf) *nf = ctx->tune[prec].nf;
+  if (dense) *dense = use_dense(ctx, prec) ? 1 : 0;
   return DWA_OK;
 }
 
@@ -1187,9 +1190,21 @@ int dwa_autotune(dwa_ctx* ctx, int prec, int reps, dwa_tune_entry* entries, int 
       HopTune c = saved;
       c.ns = ns;
       c.order = ord;
+      c.dense = false;
       cands.push_back(Cand{c, 1, -1.0});
     }
   }
+  // the dense fifth-dimension matrices (generic 8-site kernel) against the sweeps, when
+  // the sweeps are valid at all
+  if (!ctx->dense_mix)
+    for (int ord = 0; ord < ORDER_COUNT; ++ord) {
+      if (ord == ORDER_ZDOM && ctx->dims[2] % 8 != 0) continue;
+      HopTune c = saved;
+      c.ns = 8;
+      c.order = ord;
+      c.dense = true;
+      cands.push_back(Cand{c, 1, -1.0});
+    }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   DWA_HIP(hipEventCreate(&e0), "event");
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1260,8 +1275,8 @@ int dwa_autotune(dwa_ctx* ctx, int prec, int reps, dwa_tune_entry* entries, int 
   if (rc != DWA_OK) return rc;
   if (entries)
     for (size_t k = 0; k < cands.size() && int(k) < max_entries; ++k)
-      entries[k] = dwa_tune_entry{prec, cands[k].t.ns, cands[k].t.order, cands[k].t.nf, cands[k].nrhs,
-                                  cands[k].us};
+      entries[k] = dwa_tune_entry{prec, cands[k].t.ns, cands[k].t.order, cands[k].t.nf,
+                                  (cands[k].t.dense || ctx->dense_mix) ? 1 : 0, cands[k].nrhs, cands[k].us};
   if (n_entries) *n_entries = int(cands.size());
   return DWA_OK;
 }

@@ -252,7 +252,8 @@ enum HopOrder { ORDER_SLAB = 0, ORDER_LEX = 1, ORDER_ZDOM = 2, ORDER_COUNT = 3 }
 struct HopTune {
   int ns = 16;
   int order = ORDER_SLAB;
-  int nf = 1;  // fields per block when a batch is applied
+  int nf = 1;          // fields per block when a batch is applied
+  bool dense = false;  // dense fifth-dimension matrices instead of the sweeps
 };
 }  // namespace dwa
 
@@ -307,8 +308,11 @@ namespace dwa {
 inline bool hop_specialised(int Ls, bool dense) {
   return !dense && (Ls == 4 || Ls == 8 || Ls == 12 || Ls == 16);
 }
+// Dense fifth-dimension matrices for precision prec: forced for the context (a sweep
+// program failed its check, or DWA_DENSE_MIX) or chosen by the tuning.
+inline bool use_dense(const dwa_ctx* ctx, int prec) { return ctx->dense_mix || ctx->tune[prec].dense; }
 inline int hop_sites_per_block(const dwa_ctx* ctx, int prec) {
-  return hop_specialised(ctx->Ls, ctx->dense_mix) ? ctx->tune[prec].ns : 8;
+  return hop_specialised(ctx->Ls, use_dense(ctx, prec)) ? ctx->tune[prec].ns : 8;
 }
 
 // kernel launchers (kernels.hip)

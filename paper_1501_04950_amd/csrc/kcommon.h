@@ -1159,7 +1159,7 @@ void launch_smix_k(dwa_ctx* ctx, void* out, const void* in, const void* post, do
 #define DWA_SMIX(LSV, DV)                                                                    \
   hipLaunchKernelGGL((smix_kernel<S, LSV, KIND, DV>), dim3(grid, nrhs), dim3(256), 0, ctx->stream, \
                      (E*)out, (const E*)in, (const E*)post, post_coef, T, ctx->Ls, Vh, partials)
-  DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_SMIX)
+  DWA_LS_DISPATCH(ctx->Ls, use_dense(ctx, S::prec), DWA_SMIX)
 #undef DWA_SMIX
 }
 
@@ -1220,7 +1220,7 @@ int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, con
                        0, ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,      \
                        ctx->Ls, Vh, partials);                                                   \
   }
-  DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_U1)
+  DWA_LS_DISPATCH(ctx->Ls, use_dense(ctx, S::prec), DWA_U1)
 #undef DWA_U1
   if (nblocks) *nblocks = grid;
   return hip_fail(hipGetLastError(), "cg update1 launch");
@@ -1248,7 +1248,7 @@ int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevSca
     hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0, \
                        ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh);              \
   }
-  DWA_LS_DISPATCH(ctx->Ls, ctx->dense_mix, DWA_U2)
+  DWA_LS_DISPATCH(ctx->Ls, use_dense(ctx, S::prec), DWA_U2)
 #undef DWA_U2
   return hip_fail(hipGetLastError(), "cg update2 launch");
 }

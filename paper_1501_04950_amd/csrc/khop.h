@@ -17,7 +17,8 @@ int launch_hop_mix_mk(dwa_ctx* ctx, const HopDev& a, dim3 grid, dim3 block, size
     else                                                                                           \
       hipLaunchKernelGGL((hop_mix_kernel<S, NS, LSV, MODE, KIND, DV, false>), grid, block, shm, ctx->stream, a); \
   } while (0)
-  if (hop_specialised(ctx->Ls, ctx->dense_mix)) {
+  const bool dense = use_dense(ctx, S::prec);
+  if (hop_specialised(ctx->Ls, dense)) {
     switch (ctx->Ls) {
       case 4: DWA_HOPMIX(4, false); break;
       case 8: DWA_HOPMIX(8, false); break;
@@ -27,7 +28,7 @@ int launch_hop_mix_mk(dwa_ctx* ctx, const HopDev& a, dim3 grid, dim3 block, size
     return DWA_OK;
   }
   if constexpr (NS == 8) {
-    if (ctx->dense_mix) DWA_HOPMIX(0, true);
+    if (dense) DWA_HOPMIX(0, true);
     else DWA_HOPMIX(0, false);
     return DWA_OK;
   }

@@ -17,6 +17,7 @@ Tensor shapes used by the wrappers:
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 import re
 from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_size_t, c_void_p
@@ -31,6 +32,7 @@ DWA_OK, DWA_EINVAL, DWA_ENOMEM, DWA_EHIP, DWA_ENOCONV, DWA_EBREAKDOWN, DWA_ENAN,
     0, -1, -2, -3, -4, -5, -6, -7)
 DWA_F64, DWA_F32, DWA_BF16 = 0, 1, 2
 PREC = {"f64": DWA_F64, "f32": DWA_F32, "bf16": DWA_BF16}
+PREC_NAMES = {v: k for k, v in PREC.items()}
 MIXED_MODES = {"reliable": 0, "defect": 1}
 
 MIX_KINDS = {"identity": 0, "BG": 1, "N": 2, "Ginv_Iinv": 3, "g5_IinvT_Ginv": 4, "NT": 5,
@@ -62,9 +64,17 @@ class DwaError(RuntimeError):
         self.status = status
 
 
+def _load_tune_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
 class dwa_tune_entry(ctypes.Structure):
-    _fields_ = [("prec", c_int), ("ns", c_int), ("order", c_int), ("nf", c_int), ("nrhs", c_int),
-                ("us", c_double)]
+    _fields_ = [("prec", c_int), ("ns", c_int), ("order", c_int), ("nf", c_int), ("dense", c_int),
+                ("nrhs", c_int), ("us", c_double)]
 
 
 # block traversal orders of the fused hop (dwa_set_tuning)
@@ -110,8 +120,9 @@ def lib():
                                          POINTER(c_void_p), POINTER(dwa_solve_opts),
                                          POINTER(dwa_solve_stats)]),
         "dwa_autotune": (c_int, [P, c_int, c_int, POINTER(dwa_tune_entry), c_int, POINTER(c_int)]),
-        "dwa_set_tuning": (c_int, [P, c_int, c_int, c_int, c_int]),
-        "dwa_get_tuning": (c_int, [P, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
+        "dwa_set_tuning": (c_int, [P, c_int, c_int, c_int, c_int, c_int]),
+        "dwa_get_tuning": (c_int, [P, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                   POINTER(c_int)]),
         "dwa_strerror": (ctypes.c_char_p, [c_int]),
         "dwa_last_error": (ctypes.c_char_p, []),
         "dwa_debug_smatrix": (c_int, [POINTER(dwa_params), c_int, POINTER(c_double)]),
@@ -182,6 +193,7 @@ class Context:
         self.Vh = self.V // 2
         self.params = make_params(dims, Ls, M5, m, alpha, b, c, antiperiodic_t)
         self.device = torch.device("cuda", torch.cuda.current_device())
+        self._batch_nmax = 0
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -278,34 +290,59 @@ class Context:
         return out
 
     # -- tuning ---------------------------------------------------------------
-    def autotune(self, prec="f64", reps=10):
-        """Time every tile / traversal of the fused hop for one storage precision (and,
-        with a batch reserved, the fields per block of the batched hop) and keep the
-        fastest (dwa_autotune).  Returns {"ns", "order", "nf", "us", "candidates"}; us is
-        the chosen tile's single-field hop-pair time."""
+    def autotune(self, prec="f64", reps=10, cache=None):
+        """Time every tile / traversal of the fused hop for one storage precision, the
+        dense fifth-dimension matrices against the sweeps, and (with a batch reserved)
+        the fields per block of the batched hop, and keep the fastest (dwa_autotune).
+
+        cache: path of a JSON file keyed by (GPU architecture, lattice, L_s, precision,
+        batch reservation); a hit applies the stored configuration without timing, a
+        miss tunes and stores the result.  Returns {"ns", "order", "nf", "dense", "us",
+        "candidates", "cached"}; us is the chosen configuration's single-field hop-pair
+        time (None when cached)."""
         p = PREC[prec] if isinstance(prec, str) else int(prec)
-        ent = (dwa_tune_entry * 32)()
+        key = None
+        if cache is not None:
+            torch = _torch()
+            arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+            key = "|".join(str(v) for v in (arch, "x".join(map(str, self.dims)), self.Ls,
+                                            PREC_NAMES[p], self._batch_nmax))
+            data = _load_tune_cache(cache)
+            if key in data:
+                c = data[key]
+                self.set_tuning(p, c["ns"], c["order"], c["nf"], c["dense"])
+                return {**c, "us": None, "candidates": [], "cached": True}
+        ent = (dwa_tune_entry * 48)()
         n = c_int(0)
-        check(lib().dwa_autotune(self._h, p, int(reps), ent, 32, byref(n)))
+        check(lib().dwa_autotune(self._h, p, int(reps), ent, 48, byref(n)))
         names = {v: k for k, v in HOP_ORDERS.items()}
         cands = [{"ns": ent[i].ns, "order": names[ent[i].order], "nf": ent[i].nf,
-                  "nrhs": ent[i].nrhs, "us": ent[i].us} for i in range(n.value)]
-        ns, order, nf = self.get_tuning(prec)
-        us = min((c["us"] for c in cands if c["nrhs"] == 1 and c["ns"] == ns and c["order"] == order),
-                 default=None)
-        return {"ns": ns, "order": order, "nf": nf, "us": us, "candidates": cands}
+                  "dense": bool(ent[i].dense), "nrhs": ent[i].nrhs, "us": ent[i].us}
+                 for i in range(n.value)]
+        ns, order, nf, dense = self.get_tuning(prec)
+        us = min((c["us"] for c in cands if c["nrhs"] == 1 and c["ns"] == ns and c["order"] == order
+                  and c["dense"] == dense), default=None)
+        res = {"ns": ns, "order": order, "nf": nf, "dense": dense}
+        if key is not None:
+            data = _load_tune_cache(cache)
+            data[key] = res
+            tmp = f"{cache}.tmp{os.getpid()}"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return {**res, "us": us, "candidates": cands, "cached": False}
 
-    def set_tuning(self, prec, ns, order="slab", nf=1):
+    def set_tuning(self, prec, ns, order="slab", nf=1, dense=False):
         p = PREC[prec] if isinstance(prec, str) else int(prec)
         o = HOP_ORDERS[order] if isinstance(order, str) else int(order)
-        check(lib().dwa_set_tuning(self._h, p, int(ns), o, int(nf)))
+        check(lib().dwa_set_tuning(self._h, p, int(ns), o, int(nf), 1 if dense else 0))
 
     def get_tuning(self, prec):
-        """(sites per block, block order, fields per block of a batched hop)."""
+        """(sites per block, block order, fields per block of a batched hop, dense)."""
         p = PREC[prec] if isinstance(prec, str) else int(prec)
-        ns, o, nf = c_int(0), c_int(0), c_int(0)
-        check(lib().dwa_get_tuning(self._h, p, byref(ns), byref(o), byref(nf)))
-        return ns.value, {v: k for k, v in HOP_ORDERS.items()}[o.value], nf.value
+        ns, o, nf, d = c_int(0), c_int(0), c_int(0), c_int(0)
+        check(lib().dwa_get_tuning(self._h, p, byref(ns), byref(o), byref(nf), byref(d)))
+        return ns.value, {v: k for k, v in HOP_ORDERS.items()}[o.value], nf.value, bool(d.value)
 
     # -- solvers --------------------------------------------------------------
     @staticmethod
@@ -384,6 +421,7 @@ class Context:
 
     def reserve_batch(self, nmax):
         check(lib().dwa_reserve_batch(self._h, int(nmax)))
+        self._batch_nmax = int(nmax)
 
     def apply_Dbb_batch(self, x, prec="f64", out=None, norms=False):
         """D_bb on a batch of half fields x [n, ...] (dwa_apply_Dbb_batch); with norms,

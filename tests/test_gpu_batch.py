@@ -190,14 +190,22 @@ def test_autotune_configurations_agree(dims, Ls):
         ref = _dbb_pair(ctx, x, prec)
         res = ctx.autotune(prec, reps=3)
         timed = [c for c in res["candidates"] if c["us"] >= 0]
-        say(f"    {prec}: chose ns={res['ns']} {res['order']} ({res['us']:.1f} us of "
-            + ", ".join(f"{c['ns']}/{c['order']} {c['us']:.1f}" for c in timed) + ")")
+        say(f"    {prec}: chose ns={res['ns']} {res['order']} dense={res['dense']} ({res['us']:.1f} us of "
+            + ", ".join(f"{c['ns']}/{c['order']}{'/dense' if c['dense'] else ''} {c['us']:.1f}"
+                        for c in timed) + ")")
         assert timed and res["us"] == min(c["us"] for c in timed)
+        assert any(c["dense"] for c in timed) and any(not c["dense"] for c in timed)
+        tol = {"f64": 1e-13, "f32": 2e-6, "bf16": 2e-2}[prec]
         for c in timed:
-            ctx.set_tuning(prec, c["ns"], c["order"])
+            ctx.set_tuning(prec, c["ns"], c["order"], 1, c["dense"])
             got = _dbb_pair(ctx, x, prec)
-            assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), (prec, c)
-        ctx.set_tuning(prec, res["ns"], res["order"])
+            if not c["dense"]:  # the sweeps: the same arithmetic per site, so bitwise
+                assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), (prec, c)
+            else:  # the dense matrices: the same operator to rounding
+                for g, r in zip(got, ref):
+                    gf, rf = (g.float(), r.float()) if prec == "bf16" else (g, r)
+                    assert float(torch.linalg.vector_norm(gf - rf) / torch.linalg.vector_norm(rf)) < tol, c
+        ctx.set_tuning(prec, res["ns"], res["order"], res["nf"], res["dense"])
         if Ls not in (4, 8, 12, 16):
             assert {c["ns"] for c in res["candidates"]} == {8}
             with pytest.raises(dwa.DwaError):
@@ -231,11 +239,11 @@ def test_fields_per_block_agree(prec):
         x.copy_(torch.randn(x.shape, device=dev, generator=gen).to(torch.bfloat16))
     else:
         x.copy_(torch.randn(x.shape, dtype=x.dtype, device=dev, generator=gen))
-    ns, order, _ = ctx.get_tuning(prec)
-    ctx.set_tuning(prec, ns, order, 1)
+    ns, order, _, dense = ctx.get_tuning(prec)
+    ctx.set_tuning(prec, ns, order, 1, dense)
     ref, ref_n = ctx.apply_Dbb_batch(x, prec, norms=True)
     for nf in (2, 3, 4, 5, 12, 16):
-        ctx.set_tuning(prec, ns, order, nf)
+        ctx.set_tuning(prec, ns, order, nf, dense)
         y, nrm = ctx.apply_Dbb_batch(x, prec, norms=True)
         assert torch.equal(y, ref), nf
         assert nrm == ref_n, nf
@@ -246,9 +254,10 @@ def test_fields_per_block_agree(prec):
     assert {c["nf"] for c in batch} == {1, 2, 3, 4, 6, 12}
     assert res["nf"] == min((c for c in batch if c["us"] >= 0), key=lambda c: c["us"])["nf"]
     y, nrm = ctx.apply_Dbb_batch(x, prec, norms=True)
-    assert torch.equal(y, ref)
+    if not res["dense"]:
+        assert torch.equal(y, ref)
     with pytest.raises(dwa.DwaError):
-        ctx.set_tuning(prec, ns, order, 0)
+        ctx.set_tuning(prec, ns, order, 0, dense)
     ctx.close()
 
 
@@ -289,9 +298,47 @@ def test_graph_replay_equals_eager(monkeypatch):
         # the same solve with 3 fields per hop block: partial sums are grouped per field
         # and chunk either way, so the result is bitwise the same
         prec = kw.get("inner_prec", "f64")
-        ns, order, nf0 = ctx.get_tuning(prec)
-        ctx.set_tuning(prec, ns, order, 3)
+        ns, order, nf0, dense = ctx.get_tuning(prec)
+        ctx.set_tuning(prec, ns, order, 3, dense)
         y_m, st_m, rc_m = ctx.propagator_batch(eta, **kw)
-        ctx.set_tuning(prec, ns, order, nf0)
+        ctx.set_tuning(prec, ns, order, nf0, dense)
         assert rc_m == dwa.DWA_OK and torch.equal(y_m, y_g)
+    ctx.close()
+
+
+def test_dense_matrices_and_tuning_cache(tmp_path):
+    """The dense fifth-dimension matrices (a tuning choice) against the oracle: FP64 D_bb
+    and a full FP64 solve; and the JSON tuning cache: a second autotune with the same key
+    applies the stored configuration without timing."""
+    from oracle import redblack
+    dev = gpu()
+    dims, Ls = (4, 4, 4, 4), 8
+    U = synth.su3_field(dims, 0.5, 31)
+    p = redblack.Params.make(dims, Ls, -1.8, 0.05, 0.8, 1.5, 0.5)
+    rb = redblack.RedBlack(U, p)
+    ctx = dwa.Context(dims, Ls, -1.8, 0.05, 0.8, 1.5, 0.5)
+    ctx.set_links(torch.from_numpy(U).to(dev))
+    ctx.set_tuning("f64", 8, "slab", 1, True)
+    assert ctx.get_tuning("f64")[3] is True
+    x = synth.gaussian_field5(dims, Ls, 37) * rb.black
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    got = torch.zeros_like(xt)
+    ctx.unpack(ctx.apply_Dbb(ctx.pack(xt, 0, "f64"), "f64"), 0, "f64", out=got)
+    r = float(np.linalg.norm(got.cpu().numpy() - rb.Dbb(x)) / np.linalg.norm(rb.Dbb(x)))
+    say(f"[gpu] dense D_bb rel err vs oracle {r:.1e}")
+    assert r < 1e-13
+    eta = synth.gaussian_source(dims, 41)
+    y, st, rc = ctx.propagator(torch.from_numpy(eta).to(dev), tol=1e-12)
+    y_ref, _ = redblack.propagator(U, eta, p, tol=1e-12)
+    assert rc == dwa.DWA_OK
+    assert float(np.linalg.norm(y.cpu().numpy() - y_ref) / np.linalg.norm(y_ref)) < 1e-9
+    with pytest.raises(dwa.DwaError):
+        ctx.set_tuning("f64", 16, "slab", 1, True)  # dense runs the 8-site kernel
+    cache = str(tmp_path / "tune.json")
+    first = ctx.autotune("bf16", reps=2, cache=cache)
+    assert not first["cached"]
+    ctx.set_tuning("bf16", 32 if first["ns"] != 32 else 16, "lex")
+    second = ctx.autotune("bf16", reps=2, cache=cache)
+    assert second["cached"] and second["us"] is None
+    assert ctx.get_tuning("bf16") == (first["ns"], first["order"], first["nf"], first["dense"])
     ctx.close()
