@@ -237,10 +237,13 @@ int true_residual64(dwa_ctx* ctx, const void* x, const void* rhs, double rhs_nor
   const size_t n = field_elems(ctx);
   DWA_TRY(apply_dbb(ctx, DWA_F64, W[W_Q], x, W[W_OPB], W[W_OPR]));
   void* r = res_out ? res_out : W[W_RES];
-  DWA_TRY(launch_axpby(ctx, DWA_F64, r, 1.0, rhs, 0.0, n));
-  DWA_TRY(launch_axpby(ctx, DWA_F64, r, -1.0, W[W_Q], 1.0, n));
+  int nb = 0;
+  DWA_TRY(launch_residual(ctx, r, rhs, W[W_Q], n, bank(ctx, 3), &nb));
+  DWA_TRY(launch_sum_partials(ctx, bank(ctx, 3), nb, ctx->d_red));
   double rr = 0.0;
-  DWA_TRY(host_norm2(ctx, DWA_F64, r, &rr));
+  DWA_HIP(hipMemcpyAsync(&rr, ctx->d_red, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+          "norm readback");
+  DWA_HIP(hipStreamSynchronize(ctx->stream), "stream sync");
   *rel = rhs_norm > 0 ? std::sqrt(rr) / rhs_norm : 0.0;
   return DWA_OK;
 }
@@ -301,8 +304,7 @@ int mixed_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_sol
       break;
     }
     // x += |r| e  (FP64 accumulate)
-    DWA_TRY(launch_convert(ctx, DWA_F64, W[W_OPB], xacc_prec(inner), xacc_buf(ctx, inner), n, rnorm));
-    DWA_TRY(launch_axpby(ctx, DWA_F64, x, 1.0, W[W_OPB], 1.0, n));
+    DWA_TRY(launch_fold_acc(ctx, xacc_prec(inner), x, xacc_buf(ctx, inner), n, rnorm));
     DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
     ndbb += 1;
     ++outer;
@@ -419,9 +421,7 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
     }
     if (update) {
       // x += scale * x_l (FP64), x_l = 0; true residual; r_l = r / |r|
-      DWA_TRY(launch_convert(ctx, DWA_F64, W[W_OPB], xprec, xl, n, scale));
-      DWA_TRY(launch_axpby(ctx, DWA_F64, x, 1.0, W[W_OPB], 1.0, n));
-      DWA_TRY(launch_zero(ctx, xprec, xl, n));
+      DWA_TRY(launch_fold_acc(ctx, xprec, x, xl, n, scale));
       DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
       ndbb += 1;
       ++outer;
@@ -798,9 +798,18 @@ int batch_true_residual(dwa_ctx* ctx, int nr, hipStream_t st, double* res2) {
   BatchWs& w = ctx->batch;
   const size_t n = field_elems(ctx);
   DWA_TRY(apply_dbb(ctx, DWA_F64, w.f64[B_Q], w.f64[B_X], w.f64[B_OPB], w.f64[B_OPR], nr));
-  DWA_TRY(launch_axpby(ctx, DWA_F64, w.f64[B_RES], 1.0, w.f64[B_PHI], 0.0, n, nr));
-  DWA_TRY(launch_axpby(ctx, DWA_F64, w.f64[B_RES], -1.0, w.f64[B_Q], 1.0, n, nr));
-  return batch_norms(ctx, DWA_F64, w.f64[B_RES], nr, st, res2);
+  int nb = 0;
+  DWA_TRY(launch_residual(ctx, w.f64[B_RES], w.f64[B_PHI], w.f64[B_Q], n, bbank(ctx, 3), &nb, nr));
+  std::vector<double> h(size_t(nb) * nr);
+  DWA_HIP(hipMemcpyAsync(h.data(), bbank(ctx, 3), sizeof(double) * h.size(), hipMemcpyDeviceToHost, st),
+          "batch residual readback");
+  DWA_HIP(hipStreamSynchronize(st), "batch residual sync");
+  for (int f = 0; f < nr; ++f) {
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) acc += h[size_t(f) * nb + i];
+    res2[f] = acc;
+  }
+  return DWA_OK;
 }
 
 }  // namespace
@@ -1739,9 +1748,7 @@ int dwa_propagator_multi(dwa_ctx* const* ctxs, int nctx, const int* nrhs, void* 
           w.h_coef[f] = live[f] ? scale[i][f] : 0.0;
         }
         DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
-        DWA_TRY(launch_convert(ctx, DWA_F64, w.f64[B_OPB], xacc_prec(inner), w.xacc, n, 0.0, nr, w.d_coef));
-        DWA_TRY(launch_axpby(ctx, DWA_F64, w.f64[B_X], 1.0, w.f64[B_OPB], 1.0, n, nr));
-        DWA_TRY(launch_zero(ctx, xacc_prec(inner), w.xacc, n, nr));
+        DWA_TRY(launch_fold_acc(ctx, xacc_prec(inner), w.f64[B_X], w.xacc, n, 0.0, nr, w.d_coef));
         std::vector<double> r2(nr);
         DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));  // synchronises
         std::vector<double> fac(nr, 1.0);
@@ -1857,8 +1864,7 @@ int dwa_propagator_multi(dwa_ctx* const* ctxs, int nctx, const int* nrhs, void* 
           }
           // X += |r| e in FP64, then the new residuals
           DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
-          DWA_TRY(launch_convert(ctx, DWA_F64, w.f64[B_OPB], xacc_prec(inner), w.xacc, n, 0.0, nr, w.d_coef));
-          DWA_TRY(launch_axpby(ctx, DWA_F64, w.f64[B_X], 1.0, w.f64[B_OPB], 1.0, n, nr));
+          DWA_TRY(launch_fold_acc(ctx, xacc_prec(inner), w.f64[B_X], w.xacc, n, 0.0, nr, w.d_coef));
           std::vector<double> r2(nr);
           DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));
           for (int f = 0; f < nr; ++f) {

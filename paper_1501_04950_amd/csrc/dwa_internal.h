@@ -348,6 +348,12 @@ int launch_axpby(dwa_ctx* ctx, int prec, void* y, double a, const void* x, doubl
 int launch_norm2(dwa_ctx* ctx, int prec, const void* x, size_t n, double* partials, int* nblocks,
                  int nrhs = 1);
 int launch_sum_partials(dwa_ctx* ctx, const double* partials, int n, double* out);
+// X += scale x_l, x_l = 0 (x_l in FP32 or FP64; per-field scales when given)
+int launch_fold_acc(dwa_ctx* ctx, int xprec, void* X, void* xl, size_t n, double scale, int nrhs = 1,
+                    const double* scales = nullptr);
+// RES = PHI - Q in FP64 and per-block partial sums of |RES|^2 (nblocks per field)
+int launch_residual(dwa_ctx* ctx, void* res, const void* phi, const void* q, size_t n, double* partials,
+                    int* nblocks, int nrhs = 1);
 int launch_source(dwa_ctx* ctx, void* chi_b, void* chi_r, void* aux_b, void* aux_r, const void* eta);
 int launch_extract(dwa_ctx* ctx, void* y1, const void* psi_b, const void* psi_r);
 int launch_check_finite(dwa_ctx* ctx, const void* canon, size_t ncomplex, int* d_flag);

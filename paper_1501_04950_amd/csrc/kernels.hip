@@ -186,6 +186,47 @@ __global__ void __launch_bounds__(256) check_finite_kernel(const double* __restr
   if (bad) atomicOr(flag, 1);
 }
 
+// X += s x_l and x_l = 0 for every field of a batch (blockIdx.y; per-field s when a
+// table is given): the low-precision solution accumulator folded into the FP64
+// solution at a reliable update or a defect-correction step, in one pass.
+template <typename SX>
+__global__ void __launch_bounds__(256) fold_acc_kernel(double2* __restrict__ X,
+                                                       typename SX::elem* __restrict__ xl, size_t n,
+                                                       double scale, const double* __restrict__ scales) {
+  X += size_t(blockIdx.y) * n;
+  xl += size_t(blockIdx.y) * n;
+  if (scales) scale = scales[blockIdx.y];
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    const cpx<typename SX::real> v = ld<SX>(xl, i);
+    double2 x = X[i];
+    x.x += scale * double(v.re);
+    x.y += scale * double(v.im);
+    X[i] = x;
+    st<SX>(xl, i, cmk<typename SX::real>(0, 0));
+  }
+}
+
+// RES = PHI - Q (FP64) with the block partial sums of |RES|^2, per field of a batch.
+__global__ void __launch_bounds__(256) residual_kernel(double2* __restrict__ res,
+                                                       const double2* __restrict__ phi,
+                                                       const double2* __restrict__ q, size_t n,
+                                                       double* __restrict__ partials) {
+  const size_t off = size_t(blockIdx.y) * n;
+  res += off;
+  phi += off;
+  q += off;
+  double v = 0.0;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    const double2 a = phi[i], b = q[i];
+    const double2 r = make_double2(a.x - b.x, a.y - b.y);
+    res[i] = r;
+    v += r.x * r.x + r.y * r.y;
+  }
+  block_sum_to(v, &partials[blockIdx.y * gridDim.x + blockIdx.x]);
+}
+
 inline int grid_for(size_t n, int block, int cap = 65536) {
   size_t g = (n + block - 1) / block;
   if (g > (size_t)cap) g = cap;
@@ -357,6 +398,31 @@ __global__ void scale_gamma_kernel(DevScalars* s, double f, const double* fs) {
 int launch_scale_gamma(dwa_ctx* ctx, DevScalars* s, double f, int nrhs, const double* fs) {
   hipLaunchKernelGGL(scale_gamma_kernel, dim3(nrhs), dim3(64), 0, ctx->stream, s, f, fs);
   return hip_fail(hipGetLastError(), "scale gamma launch");
+}
+
+int launch_fold_acc(dwa_ctx* ctx, int xprec, void* X, void* xl, size_t n, double scale, int nrhs,
+                    const double* scales) {
+  const dim3 grid(grid_for(n, 256, 4096), nrhs);
+  if (xprec == DWA_F32)
+    hipLaunchKernelGGL(fold_acc_kernel<F32>, grid, dim3(256), 0, ctx->stream, (double2*)X, (float2*)xl, n,
+                       scale, scales);
+  else if (xprec == DWA_F64)
+    hipLaunchKernelGGL(fold_acc_kernel<F64>, grid, dim3(256), 0, ctx->stream, (double2*)X, (double2*)xl, n,
+                       scale, scales);
+  else {
+    set_error("solution accumulator must be FP32 or FP64");
+    return DWA_EINVAL;
+  }
+  return hip_fail(hipGetLastError(), "fold launch");
+}
+
+int launch_residual(dwa_ctx* ctx, void* res, const void* phi, const void* q, size_t n, double* partials,
+                    int* nblocks, int nrhs) {
+  const int g = grid_for(n, 256, 2048);
+  hipLaunchKernelGGL(residual_kernel, dim3(g, nrhs), dim3(256), 0, ctx->stream, (double2*)res,
+                     (const double2*)phi, (const double2*)q, n, partials);
+  if (nblocks) *nblocks = g;
+  return hip_fail(hipGetLastError(), "residual launch");
 }
 
 int launch_sum_partials(dwa_ctx* ctx, const double* partials, int n, double* out) {
