@@ -28,6 +28,10 @@ CASES = {
     # the largest Ls the library takes (generic kernel, register arrays of 32 slices)
     "lsmax32_2x2x2x4_ls32": ((2, 2, 2, 4), 32, -1.8, 0.05, 0.8, None, None),
     "c2_8x8x8x16_ls12": ((8, 8, 8, 16), 12, -1.8, 0.02, 0.6, 1.5, 0.5),
+    # L_s = 16 (the bench's) with 24 black sites: every tile size has a partly filled
+    # last block
+    "ls16_ragged_2x2x2x6": ((2, 2, 2, 6), 16, -1.8, 0.05, 0.8, 1.5, 0.5),
+    "ls16_4x4x4x4": ((4, 4, 4, 4), 16, -1.7, 0.03, 1.2, None, None),
 }
 
 
@@ -227,6 +231,32 @@ def test_dbb_low_precision_error(prec, bound):
     r = rel(got, ref)
     say(f"    D_bb {prec} rel err vs FP64 oracle {r:.2e}")
     assert r < bound
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["ls16_ragged_2x2x2x6", "ls16_4x4x4x4"])
+def test_dbb_bf16_ls16_tiles(name):
+    """BF16 D_bb and D_bb^dag at L_s = 16 (the bench's compiled kernels) against the
+    FP64 oracle for every tile size and block order, and bitwise the same result from
+    each of them."""
+    cs = case(name)
+    ctx = cs.ctx()
+    x = cs.black_field(21)
+    ref = cs.oracle().Dbb(x)
+    ref_d = cs.oracle().Dbb_dag(x)
+    first = None
+    for ns in (8, 16, 32):
+        for order in ("slab", "lex"):
+            ctx.set_tuning("bf16", ns, order)
+            got = _gpu_dbb(cs, ctx, x, "bf16")
+            got_d = _gpu_dbb(cs, ctx, x, "bf16", dagger=True)
+            r, rd = rel(got, ref), rel(got_d, ref_d)
+            say(f"    ns={ns} {order}: BF16 D_bb rel err {r:.2e}, dagger {rd:.2e}")
+            assert r < 2e-2 and rd < 2e-2
+            if first is None:
+                first = (got, got_d)
+            else:
+                assert np.array_equal(got, first[0]) and np.array_equal(got_d, first[1])
     ctx.close()
 
 
