@@ -299,11 +299,11 @@ def main():
 
 def batch_bench(torch, dwa, synth, dev, stream, args):
     """The batched workload: 8^4 / Ls 8, 12^3x24 / Ls 12 and 16^3x32 / Ls 16 with the 12
-    spin-colour point sources each, FP32 inner solves to 1e-10, all 36 systems in one
-    dwa_propagator_multi call, against the same 36 systems solved one at a time.  Also
-    the batched D_bb of 12 FP32 fields on 16^3x32 against 12 single applications."""
+    spin-colour point sources each, solved to 1e-10 with FP32 inner solves and again with
+    BF16 inner solves, all 36 systems in one dwa_propagator_multi call, against the same
+    36 systems solved one at a time.  Also the batched D_bb of 12 FP32 fields on
+    16^3x32 against 12 single applications."""
     bw = synth.BATCH_WORKLOAD
-    kw = dict(tol=args.tol, inner_prec="f32", delta=0.1, check_every=args.check_every)
     batches = []
     for k, lat in enumerate(bw["lattices"]):
         dims, Ls = lat["dims"], lat["Ls"]
@@ -311,42 +311,51 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
         ctx.set_links(torch.from_numpy(synth.su3_field(dims, bw["spread"], bw["seed"] + k)).to(dev))
         ctx.reserve_batch(12)
         if not args.no_tune:
-            for prec in ("f64", "f32"):
+            for prec in ("f64", "f32", "bf16"):
                 ctx.autotune(prec, reps=5)
         eta = torch.from_numpy(np.stack([synth.point_source(dims, 0, j // 3, j % 3)
                                          for j in range(12)])).to(dev)
         batches.append((ctx, eta))
-    log("batch: 3 lattices x 12 sources, FP32 inner (warmup)")
-    dwa.propagator_multi(batches, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ys, sts, rc = dwa.propagator_multi(batches, **kw)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    log(f"  batched: {t_batch:.3f} s, status {rc}")
-    for ctx, eta in batches:  # warm each context's single-solve path
-        ctx.propagator(eta[0].contiguous(), **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    seq, seq_iters = [], []
-    for ctx, eta in batches:
-        ylat, it = [], []
-        for j in range(12):
-            y, st, _ = ctx.propagator(eta[j].contiguous(), **kw)
-            ylat.append(y)
-            it.append(st["iters"])
-        seq.append(ylat)
-        seq_iters.append(it)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    log(f"  sequential: {t_seq:.3f} s")
-    diff = max(float(torch.linalg.vector_norm(ys[i][j] - seq[i][j]) / torch.linalg.vector_norm(seq[i][j]))
-               for i in range(3) for j in range(12))
-    lat = []
-    for (ctx, _), st, it in zip(batches, sts, seq_iters):
-        lat.append({"dims": list(ctx.dims), "Ls": ctx.Ls,
-                    "batch_iters": [s["iters"] for s in st], "single_iters": it,
-                    "max_rel_resid": max(s["rel_resid"] for s in st)})
+
+    def solve_both(kw, label):
+        log(f"batch: 3 lattices x 12 sources, {label} inner (warmup)")
+        dwa.propagator_multi(batches, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ys, sts, rc = dwa.propagator_multi(batches, **kw)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        log(f"  batched: {t_batch:.3f} s, status {rc}")
+        for ctx, eta in batches:  # warm each context's single-solve path
+            ctx.propagator(eta[0].contiguous(), **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seq, seq_iters = [], []
+        for ctx, eta in batches:
+            ylat, it = [], []
+            for j in range(12):
+                y, st, _ = ctx.propagator(eta[j].contiguous(), **kw)
+                ylat.append(y)
+                it.append(st["iters"])
+            seq.append(ylat)
+            seq_iters.append(it)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        log(f"  sequential: {t_seq:.3f} s")
+        diff = max(float(torch.linalg.vector_norm(ys[i][j] - seq[i][j]) / torch.linalg.vector_norm(seq[i][j]))
+                   for i in range(3) for j in range(12))
+        lat = []
+        for (ctx, _), st, it in zip(batches, sts, seq_iters):
+            lat.append({"dims": list(ctx.dims), "Ls": ctx.Ls,
+                        "batch_iters": [s["iters"] for s in st], "single_iters": it,
+                        "max_rel_resid": max(s["rel_resid"] for s in st)})
+        return {"inner": kw["inner_prec"], "delta": kw["delta"], "status": rc,
+                "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
+                "speedup": round(t_seq / t_batch, 3), "max_y1_rel_diff_batch_vs_single": diff,
+                "lattices": lat}
+
+    r32 = solve_both(dict(tol=args.tol, inner_prec="f32", delta=0.1, check_every=args.check_every), "FP32")
+    r16 = solve_both(dict(tol=args.tol, inner_prec="bf16", delta=0.3, check_every=args.check_every), "BF16")
     # batched D_bb, 12 FP32 fields on the largest lattice
     ctx = batches[2][0]
     x = torch.stack([ctx.half_field("f32") for _ in range(12)]).contiguous()
@@ -387,12 +396,12 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
         f"{batch_nf1_ms:.3f} ms), 12 single {single_ms:.3f} ms")
     for c, _ in batches:
         c.close()
-    return {"workload": "8^4/Ls8 + 12^3x24/Ls12 + 16^3x32/Ls16, 12 point sources each, "
-                        f"spread {bw['spread']}, alpha {bw['alpha']}, m {bw['m']}, FP32 inner, "
-                        f"tol {args.tol}",
-            "status": rc, "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
-            "speedup": round(t_seq / t_batch, 3), "max_y1_rel_diff_batch_vs_single": diff,
-            "lattices": lat, "dbb_batch": dbb}
+    out = {"workload": "8^4/Ls8 + 12^3x24/Ls12 + 16^3x32/Ls16, 12 point sources each, "
+                       f"spread {bw['spread']}, alpha {bw['alpha']}, m {bw['m']}, tol {args.tol}"}
+    out.update(r32)  # FP32 inner at the top level, as before
+    out["bf16_inner"] = r16
+    out["dbb_batch"] = dbb
+    return out
 
 
 def measured_traffic(kernel):
