@@ -32,6 +32,7 @@ CASES = {
     # last block
     "ls16_ragged_2x2x2x6": ((2, 2, 2, 6), 16, -1.8, 0.05, 0.8, 1.5, 0.5),
     "ls16_4x4x4x4": ((4, 4, 4, 4), 16, -1.7, 0.03, 1.2, None, None),
+    "ls12_ragged_2x2x2x6": ((2, 2, 2, 6), 12, -1.8, 0.05, 0.7, None, None),
 }
 
 
@@ -234,11 +235,14 @@ def test_dbb_low_precision_error(prec, bound):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["ls16_ragged_2x2x2x6", "ls16_4x4x4x4"])
-def test_dbb_bf16_ls16_tiles(name):
-    """BF16 D_bb and D_bb^dag at L_s = 16 (the bench's compiled kernels) against the
-    FP64 oracle for every tile size and block order, and bitwise the same result from
-    each of them."""
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("name", ["tiny_2x2x2x2_ls4", "c1_4x4x4x4_ls8", "ls12_ragged_2x2x2x6",
+                                  "ls16_ragged_2x2x2x6", "ls16_4x4x4x4"])
+def test_dbb_tiles_match_oracle(name, prec, tol):
+    """D_bb and D_bb^dag in each storage precision with every L_s that has its own
+    kernels (4, 8, 12, 16), against the FP64 oracle for every tile size and block order,
+    and bitwise the same result from each of them.  The small lattices leave every tile
+    size with a partly filled last block."""
     cs = case(name)
     ctx = cs.ctx()
     x = cs.black_field(21)
@@ -247,12 +251,12 @@ def test_dbb_bf16_ls16_tiles(name):
     first = None
     for ns in (8, 16, 32):
         for order in ("slab", "lex"):
-            ctx.set_tuning("bf16", ns, order)
-            got = _gpu_dbb(cs, ctx, x, "bf16")
-            got_d = _gpu_dbb(cs, ctx, x, "bf16", dagger=True)
+            ctx.set_tuning(prec, ns, order)
+            got = _gpu_dbb(cs, ctx, x, prec)
+            got_d = _gpu_dbb(cs, ctx, x, prec, dagger=True)
             r, rd = rel(got, ref), rel(got_d, ref_d)
-            say(f"    ns={ns} {order}: BF16 D_bb rel err {r:.2e}, dagger {rd:.2e}")
-            assert r < 2e-2 and rd < 2e-2
+            say(f"    ns={ns} {order}: {prec} D_bb rel err {r:.2e}, dagger {rd:.2e}")
+            assert r < tol and rd < tol
             if first is None:
                 first = (got, got_d)
             else:
