@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
     ap.add_argument("--no-sweep", action="store_true", help="skip the alpha sweep")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient (adjoint) timing")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default hop tiles instead of running the autotuner")
     ap.add_argument("--no-batch", action="store_true",
@@ -201,6 +202,33 @@ def main():
     if y64 is not None:
         y_err = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
 
+    # --- gradients of L = Re <eta', y_1> (adjoint state): forward solve, adjoint solve
+    # on D_bb^dag and the force kernels, with the mixed solves and with FP64 solves ----
+    grad = None
+    if not args.no_grad:
+        eta_p = torch.from_numpy(synth.gaussian_source(dims, w["seed"] + 200)).to(dev)
+        grad = {}
+        for inner in (args.inner, "f64"):
+            gkw = dict(kw, inner_prec=inner) if inner != "f64" else dict(tol=args.tol, inner_prec="f64",
+                                                                          check_every=args.check_every)
+            ctx.propagator_adjoint(eta_d, eta_p, **gkw)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g = ctx.propagator_adjoint(eta_d, eta_p, **gkw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            grad[inner] = {"time_s": round(dt, 4), "fwd_iters": g["stats"][0]["iters"],
+                           "adj_iters": g["stats"][1]["iters"],
+                           "adj_rel_resid": g["stats"][1]["rel_resid"], "status": g["status"]}
+            log(f"gradients ({inner} solves): {dt:.3f} s, iters fwd {g['stats'][0]['iters']} "
+                f"adj {g['stats'][1]['iters']}, adj resid {g['stats'][1]['rel_resid']:.1e}")
+            if inner == args.inner:
+                gU = g["U"]
+        grad["ratio_to_forward_solve"] = round(grad[args.inner]["time_s"] / mixed_s, 3)
+        grad["U_rel_diff_mixed_vs_f64"] = float(torch.linalg.vector_norm(gU - g["U"]) /
+                                                torch.linalg.vector_norm(g["U"]))
+        del g, gU
+
     # --- alpha study (Sec. 3): FP64 CGNE iteration counts n(alpha) -------------------
     sweep = None
     if not args.no_sweep:
@@ -289,6 +317,7 @@ def main():
         "dbb": {p: {k: round(v, 2) for k, v in kern[p].items()} for p in kern},
         "roofline": roofline,
         "tuning": tuning,
+        "gradients": grad,
         "alpha_sweep": sweep,
         "batch": batch,
         "cpu_baseline": cpu,

@@ -256,8 +256,10 @@ int dwa_alpha_sweep(dwa_ctx *ctx, const double *alphas, int n, void *y1, const v
  *   gb, gc host double [Ls]: dL/db_s, dL/dc_s,
  *   L      host double: the loss, y1 device [V][4][3]: the propagator.
  * Any output may be NULL.  eta and eta_prime are device complex128 [V][4][3].  opts
- * applies to the forward solve (any inner precision) and, as FP64 CGNE, to the
- * adjoint solve; stats (may be NULL) receives two entries: forward, adjoint.
+ * applies to both solves: the adjoint solve (CGLS on D_bb^dag) runs in FP64 when
+ * inner_prec is DWA_F64 and otherwise in inner_prec with FP64 reliable updates
+ * (mixed_mode is not used there; warm_start applies to the forward solve only);
+ * stats (may be NULL) receives two entries: forward, adjoint.
  * Returns DWA_ENOCONV if either solve did not converge (outputs still written). */
 int dwa_propagator_adjoint(dwa_ctx *ctx, void *gU, void *geta, double *galpha, double *gb,
                            double *gc, double *L, void *y1, const void *eta,

@@ -232,10 +232,13 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
 
 // |rhs - D_bb x| / |rhs| in FP64 (uses W_Q, W_RES, W_OPB, W_OPR)
 int true_residual64(dwa_ctx* ctx, const void* x, const void* rhs, double rhs_norm, double* rel,
-                    void* res_out) {
+                    void* res_out, bool adj = false) {
   void** W = ctx->w64;
   const size_t n = field_elems(ctx);
-  DWA_TRY(apply_dbb(ctx, DWA_F64, W[W_Q], x, W[W_OPB], W[W_OPR]));
+  if (adj)
+    DWA_TRY(apply_dbbdag(ctx, DWA_F64, W[W_Q], x, W[W_OPB], W[W_OPR]));
+  else
+    DWA_TRY(apply_dbb(ctx, DWA_F64, W[W_Q], x, W[W_OPB], W[W_OPR]));
   void* r = res_out ? res_out : W[W_RES];
   int nb = 0;
   DWA_TRY(launch_residual(ctx, r, rhs, W[W_Q], n, bank(ctx, 3), &nb));
@@ -334,7 +337,7 @@ int mixed_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_sol
 // recomputed in FP64 and replaces r_l, and CGLS continues from there (z = D_bb^dag r,
 // beta = |z|^2 / gamma).  The solve stops on the FP64 residual.
 int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_solve_opts* o,
-                   dwa_solve_stats* st) {
+                   dwa_solve_stats* st, bool adj = false) {
   void** W = ctx->w64;
   void** Lw = low_pool(ctx, inner);
   void* r = Lw[L_R];
@@ -351,6 +354,18 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   int nbA = 0, nbB = 0;
   const int check_every = o->check_every < 1 ? 1 : o->check_every;
   const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
+  // A is D_bb, or D_bb^dag for adj (the adjoint solve); the premixed input of A (u,
+  // from p) and of A^dag (w, from r) follow
+  const int mixA = adj ? MIX_G5_IINVT_GINV : MIX_BG;
+  const int mixAd = adj ? MIX_BG : MIX_G5_IINVT_GINV;
+  auto applyA = [&](void* out, const void* in, const void* pre, double* part, int* nb) {
+    return adj ? dbbdag_from_premix(ctx, inner, out, in, pre, t, part, nb)
+               : dbb_from_premix(ctx, inner, out, in, pre, t, part, nb);
+  };
+  auto applyAd = [&](void* out, const void* in, const void* pre, double* part, int* nb) {
+    return adj ? dbb_from_premix(ctx, inner, out, in, pre, t, part, nb)
+               : dbbdag_from_premix(ctx, inner, out, in, pre, t, part, nb);
+  };
 
   double b2 = 0.0;
   DWA_TRY(host_norm2(ctx, DWA_F64, rhs, &b2));
@@ -365,7 +380,7 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   int outer = 0;
   double rel = 1.0;
   if (o->warm_start) {
-    DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
+    DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES], adj));
     ndbb += 1;
   } else {
     DWA_TRY(launch_axpby(ctx, DWA_F64, W[W_RES], 1.0, rhs, 0.0, n));
@@ -379,12 +394,12 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   double scale = rel * bnorm;  // FP64 residual norm at the last update
   DWA_TRY(launch_convert(ctx, inner, r, DWA_F64, W[W_RES], n, 1.0 / scale));
   DWA_TRY(launch_zero(ctx, xprec, xl, n));
-  DWA_TRY(launch_smix(ctx, inner, MIX_G5_IINVT_GINV, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
-  DWA_TRY(dbbdag_from_premix(ctx, inner, z, r, w, t, bank(ctx, 0), &nbA));
+  DWA_TRY(launch_smix(ctx, inner, mixAd, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
   DWA_TRY(launch_norm2(ctx, inner, r, n, bank(ctx, 1), &nbB));
   DWA_TRY(launch_cg_finalize(ctx, 2, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
   DWA_TRY(launch_axpby(ctx, inner, p, 1.0, z, 0.0, n));
-  DWA_TRY(launch_smix(ctx, inner, MIX_BG, u, p, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  DWA_TRY(launch_smix(ctx, inner, mixA, u, p, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
   ndbb += 1;
 
   int k = 0, status = DWA_ENOCONV, stall = 0;
@@ -393,9 +408,9 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   double last_rel = rel;
   while (k < o->maxiter) {
     // q = D_bb p ; a ; x_l += a p ; r_l -= a q ; |r_l|^2 ; w = g5 I^-T G^-1 r_l
-    DWA_TRY(dbb_from_premix(ctx, inner, q, p, u, t, bank(ctx, 0), &nbA));
+    DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
     DWA_TRY(launch_cg_finalize(ctx, 0, sc, bank(ctx, 0), nbA, nullptr, 0));
-    DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB));
+    DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB, adj));
     ndbb += 1;
     ++k;
     bool update = false, done = false;
@@ -422,7 +437,7 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
     if (update) {
       // x += scale * x_l (FP64), x_l = 0; true residual; r_l = r / |r|
       DWA_TRY(launch_fold_acc(ctx, xprec, x, xl, n, scale));
-      DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES]));
+      DWA_TRY(true_residual64(ctx, x, rhs, bnorm, &rel, W[W_RES], adj));
       ndbb += 1;
       ++outer;
       if (trace) std::fprintf(stderr, "[dwa] update %d at k=%d: true rel %.3e\n", outer, k, rel);
@@ -447,17 +462,16 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
         DWA_TRY(launch_scale_gamma(ctx, sc, f * f));
         scale = new_scale;
         DWA_TRY(launch_convert(ctx, inner, r, DWA_F64, W[W_RES], n, 1.0 / scale));
-        DWA_TRY(launch_smix(ctx, inner, MIX_G5_IINVT_GINV, w, r, nullptr, 0.0, ctx->Ls, nullptr,
-                            nullptr));
+        DWA_TRY(launch_smix(ctx, inner, mixAd, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
         DWA_TRY(launch_norm2(ctx, inner, r, n, bank(ctx, 1), &nbB));
         rmax = 1.0;
       }
     }
     if (done) break;
     // z = D_bb^dag r_l ; beta = |z|^2 / gamma ; p = z + beta p ; u = B G p
-    DWA_TRY(dbbdag_from_premix(ctx, inner, z, r, w, t, bank(ctx, 0), &nbA));
+    DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
     DWA_TRY(launch_cg_finalize(ctx, 1, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
-    DWA_TRY(launch_cg_update2(ctx, inner, p, u, z, sc));
+    DWA_TRY(launch_cg_update2(ctx, inner, p, u, z, sc, adj));
     ndbb += 1;
   }
   st->iters = k;
@@ -1472,7 +1486,21 @@ int dwa_propagator_adjoint(dwa_ctx* ctx, void* gU, void* geta, double* galpha, d
   {
     const auto t0 = std::chrono::steady_clock::now();
     CgResult cr;
-    DWA_TRY(cgls(ctx, DWA_F64, W[W_X], W[W_PHI], false, o->tol, o->maxiter, o->check_every, &cr, true));
+    if (o->inner_prec == DWA_F64) {
+      DWA_TRY(cgls(ctx, DWA_F64, W[W_X], W[W_PHI], false, o->tol, o->maxiter, o->check_every, &cr, true));
+    } else {
+      // the forward solve's inner precision, with reliable updates, from x = 0
+      dwa_solve_opts oa = *o;
+      oa.warm_start = 0;
+      dwa_solve_stats sa{};
+      const int rc = reliable_solve(ctx, o->inner_prec, W[W_X], W[W_PHI], &oa, &sa, true);
+      if (rc != DWA_OK && rc != DWA_ENOCONV && rc != DWA_EBREAKDOWN) return rc;
+      cr.iters = sa.iters;
+      cr.converged = sa.converged;
+      cr.breakdown = rc == DWA_EBREAKDOWN;
+      cr.n_dbb = sa.n_Dbb;
+      st[1].outer = sa.outer;
+    }
     double g2 = 0.0;
     DWA_TRY(host_norm2(ctx, DWA_F64, W[W_PHI], &g2));
     DWA_TRY(apply_dbbdag(ctx, DWA_F64, W[W_Q], W[W_X], W[W_OPB], W[W_OPR]));

@@ -1202,19 +1202,14 @@ int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, con
   using EX = typename XAcc<S>::type::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
   const int grid = (int)((6u * Vh + 255) / 256);
-  if (adj && S::prec != DWA_F64) {
-    set_error("CGLS on D_bb^dag runs in FP64 only");
-    return DWA_EINVAL;
-  }
   // w is the premixed input of the operator applied to r next: D_bb^dag (normal CGLS)
   // or, for CGLS on D_bb^dag, D_bb
   const MixTables T = mix_tables<S>(ctx, adj ? MIX_BG : MIX_G5_IINVT_GINV);
 #define DWA_U1(LSV, DV)                                                                          \
   if (adj) {                                                                                     \
-    if constexpr (S::prec == DWA_F64)                                                            \
-      hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0, \
-                         ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,       \
-                         ctx->Ls, Vh, partials);                                                 \
+    hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0,   \
+                       ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,         \
+                       ctx->Ls, Vh, partials);                                                   \
   } else {                                                                                       \
     hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid, nrhs), dim3(256), \
                        0, ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,      \
@@ -1232,18 +1227,13 @@ int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevSca
   using E = typename S::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
   const int grid = (int)((6u * Vh + 255) / 256);
-  if (adj && S::prec != DWA_F64) {
-    set_error("CGLS on D_bb^dag runs in FP64 only");
-    return DWA_EINVAL;
-  }
   // u is the premixed input of the operator applied to p next: D_bb (normal CGLS) or,
   // for CGLS on D_bb^dag, D_bb^dag
   const MixTables T = mix_tables<S>(ctx, adj ? MIX_G5_IINVT_GINV : MIX_BG);
 #define DWA_U2(LSV, DV)                                                                        \
   if (adj) {                                                                                   \
-    if constexpr (S::prec == DWA_F64)                                                          \
-      hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid, nrhs), \
-                         dim3(256), 0, ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh); \
+    hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid, nrhs),     \
+                       dim3(256), 0, ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh);  \
   } else {                                                                                     \
     hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0, \
                        ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh);              \

@@ -201,3 +201,26 @@ def test_autograd_function(c5):
     adj = float(torch.sum(torch.conj(U2.grad) * d).real)
     say(f"    |y|^2 link dir: fd {fd:.9e} autograd {adj:.9e}")
     _close(fd, adj, float(L2))
+
+
+@pytest.mark.parametrize("inner,delta", [("f32", 0.05), ("bf16", 0.3)])
+def test_c5_mixed_precision_gradients(c5, inner, delta):
+    """Both solves in FP32 or BF16 storage with FP64 reliable updates (tol 1e-10): the
+    adjoint solve's FP64 residual meets the tolerance and every gradient agrees with
+    the FP64 solves' (tol 1e-13) to the accuracy that tolerance allows."""
+    ctx, ref = c5["ctx"], c5["g"]
+    say(f"[gpu] c5 adjoint gradients, {inner} inner")
+    g = ctx.propagator_adjoint(c5["eta"], c5["eta_p"], tol=1e-10, inner_prec=inner, delta=delta,
+                               check_every=5)
+    st = g["stats"]
+    say(f"    iters fwd {st[0]['iters']} adj {st[1]['iters']} (FP64 {ref['stats'][1]['iters']}); "
+        f"adj resid {st[1]['rel_resid']:.1e}")
+    assert g["status"] == dwa.DWA_OK
+    assert st[1]["rel_resid"] <= 1e-10
+    assert abs(g["L"] - ref["L"]) <= 1e-8 * abs(ref["L"])
+    errs = {"U": rel(g["U"].cpu().numpy(), ref["U"].cpu().numpy()),
+            "eta": rel(g["eta"].cpu().numpy(), ref["eta"].cpu().numpy()),
+            "b": rel(g["b"], ref["b"]), "c": rel(g["c"], ref["c"])}
+    say(f"    rel errors vs FP64 solves {errs}")
+    for k, e in errs.items():
+        assert e < 1e-7, (k, e)
