@@ -152,8 +152,8 @@ def test_dbb_matches_oracle(name):
 def test_full_size_dbb_matches_oracle():
     """The bench workload at its full size (16^3 x 32, L_s = 16, APE-smeared links,
     alpha = 1) in the configuration bench.py times (autotuned tile and block order):
-    the FP64 D_bb of one seeded black field against the oracle's, element by element
-    (one oracle application, about 35 s of host time), and <y, D_bb x> =
+    the FP64, FP32 and BF16 D_bb of one seeded black field against the oracle's, element
+    by element (one oracle application, about 35 s of host time), and <y, D_bb x> =
     <D_bb^dag y, x> for the GPU operators (FP64, and FP32 / BF16 to their rounding)."""
     name = "c3_16x16x16x32_ls16"
     w = synth.WORKLOADS[name]
@@ -178,6 +178,13 @@ def test_full_size_dbb_matches_oracle():
     r = rel(got.cpu().numpy(), ref)
     say(f"    full-size D_bb rel err {r:.2e} (tuning f64 {ctx.get_tuning('f64')})")
     assert r < 1e-13
+    # the low-precision operators in the tuned configurations the solves use
+    for prec, tol in (("f32", 2e-6), ("bf16", 2e-2)):
+        lo = torch.zeros_like(xt)
+        ctx.unpack(ctx.apply_Dbb(ctx.pack(xt, 0, prec), prec), 0, prec, out=lo)
+        rl = rel(lo.cpu().numpy(), ref)
+        say(f"    full-size {prec} D_bb rel err vs FP64 oracle {rl:.2e} (tuning {ctx.get_tuning(prec)})")
+        assert rl < tol
     for prec, tol in (("f64", 1e-13), ("f32", 1e-6), ("bf16", 2e-2)):
         xp, yp = ctx.pack(xt, 0, prec), ctx.pack(yt, 0, prec)
         lhs = torch.zeros_like(xt)
