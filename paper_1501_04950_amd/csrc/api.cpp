@@ -215,9 +215,9 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
     }
     // q = A p (premixed u), |q|^2, a = gamma / |q|^2
     DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
-    DWA_TRY(launch_cg_finalize(ctx, 0, sc, bank(ctx, 0), nbA, nullptr, 0));
-    // x += a p ; r -= a q ; |r|^2 ; w = premix of r for A^dag
-    DWA_TRY(launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB, adj));
+    // (a from those partials inside update 1) x += a p ; r -= a q ; |r|^2 ;
+    // w = premix of r for A^dag
+    DWA_TRY(launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA));
     // z = A^dag r, beta = |z|^2 / gamma
     DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
     DWA_TRY(launch_cg_finalize(ctx, 1, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
@@ -407,10 +407,10 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   double rmax = 1.0;  // |r_l| (scaled units) at the last update
   double last_rel = rel;
   while (k < o->maxiter) {
-    // q = D_bb p ; a ; x_l += a p ; r_l -= a q ; |r_l|^2 ; w = g5 I^-T G^-1 r_l
+    // q = D_bb p ; (a from its |q|^2 partials inside update 1) x_l += a p ; r_l -= a q ;
+    // |r_l|^2 ; w = g5 I^-T G^-1 r_l
     DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
-    DWA_TRY(launch_cg_finalize(ctx, 0, sc, bank(ctx, 0), nbA, nullptr, 0));
-    DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB, adj));
+    DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA));
     ndbb += 1;
     ++k;
     bool update = false, done = false;

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dwa_internal.h"
+#include "kreduce.h"
 
 namespace dwa {
 
@@ -95,28 +96,6 @@ __device__ __forceinline__ lcpx<R> to_lds(cpx<R> v) {
 template <typename R>
 __device__ __forceinline__ cpx<R> from_lds(lcpx<R> v) {
   return cmk<R>(v.x, v.y);
-}
-
-// ---------------------------------------------------------------------------
-// wave64 + LDS block reduction of a double, fixed order (deterministic)
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ void block_sum_to(double v, double* out_slot) {
-  __shared__ double wsum[16];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-  v = wave_sum(v);
-  if (lane == 0) wsum[wid] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < nw; ++i) t += wsum[i];
-    *out_slot = t;
-  }
 }
 
 // Scalar-loadable view of a read-only table: the constant address space tells the
@@ -809,16 +788,21 @@ __device__ __forceinline__ void st_stream(typename S::elem* p, size_t i, cpx<typ
   }
 }
 
-// CGLS update 1: x += a p ; r -= a q ; |r|^2 ; w = (g5 I^-T G^-1) r
+// CGLS update 1: x += a p ; r -= a q ; |r|^2 ; w = (g5 I^-T G^-1) r.
+// With qparts (the nq block partials of |q|^2 per field), every block sums them itself
+// in the finalize kernel's order and takes a = gamma / |q|^2, and block 0 stores qq, a
+// and the breakdown flag for the host: the finalize launch between the second hop and
+// this update is saved.  Otherwise a comes from the scalars.
 template <typename S, int LS, bool DENSE, int PK>
 __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type::elem* __restrict__ x,
                                                          typename S::elem* __restrict__ r,
                                                          typename S::elem* __restrict__ w,
                                                          const typename S::elem* __restrict__ p,
                                                          const typename S::elem* __restrict__ q,
-                                                         const DevScalars* __restrict__ sc,
+                                                         DevScalars* __restrict__ sc,
                                                          MixTables P, int Ls_rt, unsigned Vh,
-                                                         double* partials) {
+                                                         double* partials,
+                                                         const double* __restrict__ qparts, int nq) {
   using R = RealOf<S>;
   constexpr int LSM = LS > 0 ? LS : 32;
   const int Ls = LS > 0 ? LS : Ls_rt;
@@ -832,9 +816,22 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type:
     q += roff;
     sc += blockIdx.y;
   }
+  double ad;
+  if (qparts) {
+    const double qq = sum_partials_block(qparts + size_t(blockIdx.y) * nq, nq);
+    const bool bad = !(qq > 0.0) || !isfinite(qq);
+    ad = (!sc->active || bad) ? 0.0 : sc->gamma / qq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->qq = qq;
+      sc->a = ad;
+      if (sc->active && bad) sc->flags |= 1;
+    }
+  } else {
+    ad = sc->a;
+  }
   double nrm = 0.0;
   if (live) {
-    const R a = (R)sc->a;
+    const R a = (R)ad;
 #pragma unroll
     for (int ch = 0; ch < 2; ++ch) {
       const unsigned comp = ch * 6 + c6;
@@ -1197,7 +1194,8 @@ int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* 
 
 template <typename S>
 int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, const void* q,
-                     const DevScalars* s, double* partials, int* nblocks, bool adj, int nrhs) {
+                     DevScalars* s, double* partials, int* nblocks, bool adj, int nrhs,
+                     const double* qparts, int nq) {
   using E = typename S::elem;
   using EX = typename XAcc<S>::type::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
@@ -1209,11 +1207,11 @@ int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, con
   if (adj) {                                                                                     \
     hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0,   \
                        ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,         \
-                       ctx->Ls, Vh, partials);                                                   \
+                       ctx->Ls, Vh, partials, qparts, nq);                                       \
   } else {                                                                                       \
     hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid, nrhs), dim3(256), \
                        0, ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,      \
-                       ctx->Ls, Vh, partials);                                                   \
+                       ctx->Ls, Vh, partials, qparts, nq);                                                   \
   }
   DWA_LS_DISPATCH(ctx->Ls, use_dense(ctx, S::prec), DWA_U1)
 #undef DWA_U1
@@ -1302,7 +1300,7 @@ int convert_p(dwa_ctx* ctx, void* out, const void* in, size_t n, double scale, i
   template int launch_smix_p<S>(dwa_ctx*, int, void*, const void*, const void*, double, int,    \
                                 double*, int*, int);                                            \
   template int launch_update1_p<S>(dwa_ctx*, void*, void*, void*, const void*, const void*,     \
-                                   const DevScalars*, double*, int*, bool, int);                \
+                                   DevScalars*, double*, int*, bool, int, const double*, int);  \
   template int launch_update2_p<S>(dwa_ctx*, void*, void*, const void*, const DevScalars*, bool, \
                                    int);                                                        \
   template int norm2_p<S>(dwa_ctx*, const void*, size_t, double*, int*, int);                   \

@@ -8,57 +8,13 @@
 #include <type_traits>
 
 #include "dwa_internal.h"
+#include "kreduce.h"
 
 namespace dwa {
 
 namespace {
 
 constexpr int RED_THREADS = 256;
-
-// ---------------------------------------------------------------------------
-// wave64 + LDS block reduction of a double, fixed order (deterministic)
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ void block_sum_to(double v, double* out_slot) {
-  __shared__ double wsum[16];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-  v = wave_sum(v);
-  if (lane == 0) wsum[wid] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < nw; ++i) t += wsum[i];
-    *out_slot = t;
-  }
-}
-
-__device__ double sum_partials_block(const double* part, int n) {
-  // Thread k adds part[k], part[k + 256], ... in that order.  The loads of a group of
-  // 8 are independent and go out together: the partials were just written by blocks on
-  // every XCD, so each is a round trip to the Infinity Cache or HBM, and a loop that
-  // waited for each in turn spent most of the kernel on them.
-  constexpr int U = 8;
-  double v = 0.0;
-  for (int base = 0; base < n; base += U * blockDim.x) {
-    double t[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * int(blockDim.x) + int(threadIdx.x);
-      t[u] = i < n ? part[i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) v += t[u];
-  }
-  __shared__ double res;
-  block_sum_to(v, &res);
-  __syncthreads();
-  return res;
-}
 
 // which: 0 -> qq, a = gamma/qq ; 1 -> zz (bank a), rr (bank b), beta, gamma ;
 //        2 -> init: gamma = sum(a), rr = b2 = sum(b) ; 3 -> aux = sum(a) ; 4 -> rr = sum(a)
@@ -312,21 +268,22 @@ int launch_smix(dwa_ctx* ctx, int prec, int mix, void* out, const void* in, cons
                                        nblocks_out, nrhs));
 }
 int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
-                      const void* q, const DevScalars* s, double* partials, int* nblocks, bool adj,
-                      int nrhs) {
+                      const void* q, DevScalars* s, double* partials, int* nblocks, bool adj,
+                      int nrhs, const double* qparts, int nq) {
   if (nrhs > 1 && serial("up1")) {
     const size_t n = field_elems(ctx);
     for (int f = 0; f < nrhs; ++f) {
       int nb = 0;
       int rc = launch_cg_update1(ctx, prec, fshift(x, xacc_prec(prec), n, f), fshift(r, prec, n, f),
                                  fshift(w, prec, n, f), fshift(p, prec, n, f), fshift(q, prec, n, f), s + f,
-                                 partials + size_t(f) * ((6 * ctx->Vh + 255) / 256), &nb, adj, 1);
+                                 partials + size_t(f) * ((6 * ctx->Vh + 255) / 256), &nb, adj, 1,
+                                 qparts ? qparts + size_t(f) * nq : nullptr, nq);
       if (rc) return rc;
       if (nblocks) *nblocks = nb;
     }
     return DWA_OK;
   }
-  DWA_DISPATCH(prec, launch_update1_p<S_>(ctx, x, r, w, p, q, s, partials, nblocks, adj, nrhs));
+  DWA_DISPATCH(prec, launch_update1_p<S_>(ctx, x, r, w, p, q, s, partials, nblocks, adj, nrhs, qparts, nq));
 }
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
                       const DevScalars* s, bool adj, int nrhs) {
