@@ -597,8 +597,9 @@ int batch_first_half(BatchSys& b) {
   DevScalars* sc = ctx->batch.d_scal;
   int nbA = 0, nbB = 0;
   DWA_TRY(dbb_from_premix(ctx, b.prec, b.q, b.p, b.u, b.t, bbank(ctx, 0), &nbA, b.nr));
-  DWA_TRY(launch_cg_finalize(ctx, 0, sc, bbank(ctx, 0), nbA, nullptr, 0, b.nr));
-  DWA_TRY(launch_cg_update1(ctx, b.prec, b.x, b.r, b.w, b.p, b.q, sc, bbank(ctx, 1), &nbB, false, b.nr));
+  // a = gamma / |q|^2 per field is summed inside update 1 from the hop's partials
+  DWA_TRY(launch_cg_update1(ctx, b.prec, b.x, b.r, b.w, b.p, b.q, sc, bbank(ctx, 1), &nbB, false, b.nr,
+                            bbank(ctx, 0), nbA));
   b.nb_r = nbB;  // |r|^2 partials: summed into rr only before a host check
   b.n_dbb += b.nr;
   return DWA_OK;
