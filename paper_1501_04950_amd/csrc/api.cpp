@@ -154,7 +154,7 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
   void* t = W[p64 ? W_T : L_T];
   const size_t n = field_elems(ctx);
   DevScalars* sc = ctx->d_scal;
-  int nbA = 0, nbB = 0;
+  int nbA = 0, nbB = 0, nbZ = 0;  // partials: bank 0 |q|^2, bank 1 |r|^2, bank 2 |z|^2
   if (check_every < 1) check_every = 1;
 
   if (warm && !p64) {
@@ -185,9 +185,9 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
   }
   // z = A^dag r, gamma = |z|^2, |rhs|^2
   DWA_TRY(launch_smix(ctx, prec, mixAd, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
-  DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
+  DWA_TRY(applyAd(z, r, w, bank(ctx, 2), &nbZ));
   DWA_TRY(launch_norm2(ctx, prec, rhs, n, bank(ctx, 1), &nbB));
-  DWA_TRY(launch_cg_finalize(ctx, 2, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
+  DWA_TRY(launch_cg_finalize(ctx, 2, sc, bank(ctx, 2), nbZ, bank(ctx, 1), nbB));
   if (warm) {
     DWA_TRY(launch_norm2(ctx, prec, r, n, bank(ctx, 1), &nbB));
     DWA_TRY(launch_cg_finalize(ctx, 4, sc, bank(ctx, 1), nbB, nullptr, 0));
@@ -200,6 +200,8 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
   int k = 0;
   for (;;) {
     if (k % check_every == 0 || k >= maxiter) {
+      // |r|^2 from the last update 1's partials (at k = 0 the set-up's value stands)
+      if (k > 0) DWA_TRY(launch_cg_finalize(ctx, 4, sc, bank(ctx, 1), nbB, nullptr, 0));
       DWA_TRY(read_scalars(ctx));
       const DevScalars& h = *ctx->h_scal;
       if (h.flags) {
@@ -217,12 +219,13 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
     DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
     // (a from those partials inside update 1) x += a p ; r -= a q ; |r|^2 ;
     // w = premix of r for A^dag
-    DWA_TRY(launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA));
-    // z = A^dag r, beta = |z|^2 / gamma
-    DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
-    DWA_TRY(launch_cg_finalize(ctx, 1, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
-    // p = z + beta p ; u = premix of p for A
-    DWA_TRY(launch_cg_update2(ctx, prec, p, u, z, sc, adj));
+    // (gamma = |z|^2 from the current z's partials, also inside update 1)
+    DWA_TRY(launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA,
+                              bank(ctx, 2), nbZ));
+    // z = A^dag r ; (beta = |z|^2 / gamma inside update 2) p = z + beta p ;
+    // u = premix of p for A
+    DWA_TRY(applyAd(z, r, w, bank(ctx, 2), &nbZ));
+    DWA_TRY(launch_cg_update2(ctx, prec, p, u, z, sc, adj, 1, bank(ctx, 2), nbZ));
     res->n_dbb += 2;
     ++k;
   }
@@ -351,7 +354,7 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   const int xprec = xacc_prec(inner);
   const size_t n = field_elems(ctx);
   DevScalars* sc = ctx->d_scal;
-  int nbA = 0, nbB = 0;
+  int nbA = 0, nbB = 0, nbZ = 0;  // partials: bank 0 |q|^2, bank 1 |r|^2, bank 2 |z|^2
   const int check_every = o->check_every < 1 ? 1 : o->check_every;
   const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
   // A is D_bb, or D_bb^dag for adj (the adjoint solve); the premixed input of A (u,
@@ -395,9 +398,9 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   DWA_TRY(launch_convert(ctx, inner, r, DWA_F64, W[W_RES], n, 1.0 / scale));
   DWA_TRY(launch_zero(ctx, xprec, xl, n));
   DWA_TRY(launch_smix(ctx, inner, mixAd, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
-  DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
+  DWA_TRY(applyAd(z, r, w, bank(ctx, 2), &nbZ));
   DWA_TRY(launch_norm2(ctx, inner, r, n, bank(ctx, 1), &nbB));
-  DWA_TRY(launch_cg_finalize(ctx, 2, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
+  DWA_TRY(launch_cg_finalize(ctx, 2, sc, bank(ctx, 2), nbZ, bank(ctx, 1), nbB));
   DWA_TRY(launch_axpby(ctx, inner, p, 1.0, z, 0.0, n));
   DWA_TRY(launch_smix(ctx, inner, mixA, u, p, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
   ndbb += 1;
@@ -410,7 +413,8 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
     // q = D_bb p ; (a from its |q|^2 partials inside update 1) x_l += a p ; r_l -= a q ;
     // |r_l|^2 ; w = g5 I^-T G^-1 r_l
     DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
-    DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA));
+    DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA,
+                              bank(ctx, 2), nbZ));
     ndbb += 1;
     ++k;
     bool update = false, done = false;
@@ -468,10 +472,9 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
       }
     }
     if (done) break;
-    // z = D_bb^dag r_l ; beta = |z|^2 / gamma ; p = z + beta p ; u = B G p
-    DWA_TRY(applyAd(z, r, w, bank(ctx, 0), &nbA));
-    DWA_TRY(launch_cg_finalize(ctx, 1, sc, bank(ctx, 0), nbA, bank(ctx, 1), nbB));
-    DWA_TRY(launch_cg_update2(ctx, inner, p, u, z, sc, adj));
+    // z = D_bb^dag r_l ; (beta = |z|^2 / gamma inside update 2) p = z + beta p ; u = B G p
+    DWA_TRY(applyAd(z, r, w, bank(ctx, 2), &nbZ));
+    DWA_TRY(launch_cg_update2(ctx, inner, p, u, z, sc, adj, 1, bank(ctx, 2), nbZ));
     ndbb += 1;
   }
   st->iters = k;

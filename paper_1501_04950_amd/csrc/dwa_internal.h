@@ -361,12 +361,16 @@ int launch_check_finite(dwa_ctx* ctx, const void* canon, size_t ncomplex, int* d
 // CGLS building blocks (templated on precision inside kernels.hip).  In update1, x
 // has storage xacc_prec(prec); the other fields have storage prec.
 // adj = true runs the updates of CGLS on D_bb^dag (premixes swapped).  With qparts
-// (nq partials of |q|^2 per field) update 1 also does the finalize of a = gamma/|q|^2.
+// (nq partials of |q|^2 per field) update 1 also does the finalize of a = gamma/|q|^2,
+// and with zparts (nz partials of |z|^2) it takes gamma from them; with zparts update 2
+// does the finalize of beta = |z|^2 / gamma.
 int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
                       const void* q, DevScalars* s, double* partials, int* nblocks,
-                      bool adj = false, int nrhs = 1, const double* qparts = nullptr, int nq = 0);
+                      bool adj = false, int nrhs = 1, const double* qparts = nullptr, int nq = 0,
+                      const double* zparts = nullptr, int nz = 0);
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
-                      const DevScalars* s, bool adj = false, int nrhs = 1);
+                      DevScalars* s, bool adj = false, int nrhs = 1, const double* zparts = nullptr,
+                      int nz = 0);
 // one block per field: s[r] from partials_a[r * na ...] and partials_b[r * nb ...]
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* partials_a, int na,
                        const double* partials_b, int nb, int nrhs = 1);
@@ -391,9 +395,10 @@ template <typename S> int launch_hop_p(dwa_ctx*, const HopOp&, int*);
 template <typename S> int launch_smix_p(dwa_ctx*, int, void*, const void*, const void*, double, int,
                                         double*, int*, int);
 template <typename S> int launch_update1_p(dwa_ctx*, void*, void*, void*, const void*, const void*,
-                                           DevScalars*, double*, int*, bool, int, const double*, int);
-template <typename S> int launch_update2_p(dwa_ctx*, void*, void*, const void*, const DevScalars*,
-                                           bool, int);
+                                           DevScalars*, double*, int*, bool, int, const double*, int,
+                                           const double*, int);
+template <typename S> int launch_update2_p(dwa_ctx*, void*, void*, const void*, DevScalars*,
+                                           bool, int, const double*, int);
 template <typename S> int norm2_p(dwa_ctx*, const void*, size_t, double*, int*, int);
 template <typename S> int axpby_p(dwa_ctx*, void*, double, const void*, double, size_t, int,
                                   const double*);

@@ -792,7 +792,9 @@ __device__ __forceinline__ void st_stream(typename S::elem* p, size_t i, cpx<typ
 // With qparts (the nq block partials of |q|^2 per field), every block sums them itself
 // in the finalize kernel's order and takes a = gamma / |q|^2, and block 0 stores qq, a
 // and the breakdown flag for the host: the finalize launch between the second hop and
-// this update is saved.  Otherwise a comes from the scalars.
+// this update is saved.  Otherwise a comes from the scalars.  With zparts as well (the
+// nz partials of |z|^2 of the current z = A^dag r), gamma = |z|^2 is summed here too
+// and block 0 stores it (update 2 of this step divides by it).
 template <typename S, int LS, bool DENSE, int PK>
 __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type::elem* __restrict__ x,
                                                          typename S::elem* __restrict__ r,
@@ -802,7 +804,8 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type:
                                                          DevScalars* __restrict__ sc,
                                                          MixTables P, int Ls_rt, unsigned Vh,
                                                          double* partials,
-                                                         const double* __restrict__ qparts, int nq) {
+                                                         const double* __restrict__ qparts, int nq,
+                                                         const double* __restrict__ zparts, int nz) {
   using R = RealOf<S>;
   constexpr int LSM = LS > 0 ? LS : 32;
   const int Ls = LS > 0 ? LS : Ls_rt;
@@ -819,11 +822,13 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type:
   double ad;
   if (qparts) {
     const double qq = sum_partials_block(qparts + size_t(blockIdx.y) * nq, nq);
+    const double gamma = zparts ? sum_partials_block(zparts + size_t(blockIdx.y) * nz, nz) : sc->gamma;
     const bool bad = !(qq > 0.0) || !isfinite(qq);
-    ad = (!sc->active || bad) ? 0.0 : sc->gamma / qq;
+    ad = (!sc->active || bad) ? 0.0 : gamma / qq;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->qq = qq;
       sc->a = ad;
+      if (zparts) sc->gamma = gamma;
       if (sc->active && bad) sc->flags |= 1;
     }
   } else {
@@ -859,13 +864,18 @@ __global__ void __launch_bounds__(256) cg_update1_kernel(typename XAcc<S>::type:
   if (partials) block_sum_to(nrm, &partials[blockIdx.y * gridDim.x + blockIdx.x]);
 }
 
-// CGLS update 2: p = z + beta p ; u = (B G) p
+// CGLS update 2: p = z + beta p ; u = (B G) p.  With zparts (the nz partials of |z|^2
+// per field) every block sums them itself, in the finalize kernel's order, and takes
+// beta = |z|^2 / gamma; block 0 stores zz, beta and the breakdown flag.  gamma keeps
+// the previous |z|^2 until the next update 1 replaces it.  Otherwise beta comes from
+// the scalars.
 template <typename S, int LS, bool DENSE, int PK>
 __global__ void __launch_bounds__(256) cg_update2_kernel(typename S::elem* __restrict__ p,
                                                          typename S::elem* __restrict__ u,
                                                          const typename S::elem* __restrict__ z,
-                                                         const DevScalars* __restrict__ sc,
-                                                         MixTables P, int Ls_rt, unsigned Vh) {
+                                                         DevScalars* __restrict__ sc,
+                                                         MixTables P, int Ls_rt, unsigned Vh,
+                                                         const double* __restrict__ zparts, int nz) {
   using R = RealOf<S>;
   constexpr int LSM = LS > 0 ? LS : 32;
   const int Ls = LS > 0 ? LS : Ls_rt;
@@ -877,8 +887,21 @@ __global__ void __launch_bounds__(256) cg_update2_kernel(typename S::elem* __res
     z += roff;
     sc += blockIdx.y;
   }
+  double bd;
+  if (zparts) {
+    const double zz = sum_partials_block(zparts + size_t(blockIdx.y) * nz, nz);
+    const bool bad = !isfinite(zz) || !(sc->gamma > 0.0);
+    bd = (!sc->active || bad) ? 0.0 : zz / sc->gamma;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->zz = zz;
+      sc->beta = bd;
+      if (sc->active && bad) sc->flags |= 2;
+    }
+  } else {
+    bd = sc->beta;
+  }
   if (!live) return;
-  const R beta = (R)sc->beta;
+  const R beta = (R)bd;
 #pragma unroll
   for (int ch = 0; ch < 2; ++ch) {
     const unsigned comp = ch * 6 + c6;
@@ -1195,7 +1218,7 @@ int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* 
 template <typename S>
 int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, const void* q,
                      DevScalars* s, double* partials, int* nblocks, bool adj, int nrhs,
-                     const double* qparts, int nq) {
+                     const double* qparts, int nq, const double* zparts, int nz) {
   using E = typename S::elem;
   using EX = typename XAcc<S>::type::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
@@ -1207,11 +1230,11 @@ int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, con
   if (adj) {                                                                                     \
     hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0,   \
                        ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,         \
-                       ctx->Ls, Vh, partials, qparts, nq);                                       \
+                       ctx->Ls, Vh, partials, qparts, nq, zparts, nz);                           \
   } else {                                                                                       \
     hipLaunchKernelGGL((cg_update1_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid, nrhs), dim3(256), \
                        0, ctx->stream, (EX*)x, (E*)r, (E*)w, (const E*)p, (const E*)q, s, T,      \
-                       ctx->Ls, Vh, partials, qparts, nq);                                                   \
+                       ctx->Ls, Vh, partials, qparts, nq, zparts, nz);                                                   \
   }
   DWA_LS_DISPATCH(ctx->Ls, use_dense(ctx, S::prec), DWA_U1)
 #undef DWA_U1
@@ -1220,8 +1243,8 @@ int launch_update1_p(dwa_ctx* ctx, void* x, void* r, void* w, const void* p, con
 }
 
 template <typename S>
-int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevScalars* s, bool adj,
-                     int nrhs) {
+int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, DevScalars* s, bool adj,
+                     int nrhs, const double* zparts, int nz) {
   using E = typename S::elem;
   const unsigned Vh = (unsigned)ctx->Vh;
   const int grid = (int)((6u * Vh + 255) / 256);
@@ -1231,10 +1254,11 @@ int launch_update2_p(dwa_ctx* ctx, void* p, void* u, const void* z, const DevSca
 #define DWA_U2(LSV, DV)                                                                        \
   if (adj) {                                                                                   \
     hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_G5_IINVT_GINV>), dim3(grid, nrhs),     \
-                       dim3(256), 0, ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh);  \
+                       dim3(256), 0, ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh,   \
+                       zparts, nz);                                                            \
   } else {                                                                                     \
     hipLaunchKernelGGL((cg_update2_kernel<S, LSV, DV, MIX_BG>), dim3(grid, nrhs), dim3(256), 0, \
-                       ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh);              \
+                       ctx->stream, (E*)p, (E*)u, (const E*)z, s, T, ctx->Ls, Vh, zparts, nz);  \
   }
   DWA_LS_DISPATCH(ctx->Ls, use_dense(ctx, S::prec), DWA_U2)
 #undef DWA_U2
@@ -1300,9 +1324,10 @@ int convert_p(dwa_ctx* ctx, void* out, const void* in, size_t n, double scale, i
   template int launch_smix_p<S>(dwa_ctx*, int, void*, const void*, const void*, double, int,    \
                                 double*, int*, int);                                            \
   template int launch_update1_p<S>(dwa_ctx*, void*, void*, void*, const void*, const void*,     \
-                                   DevScalars*, double*, int*, bool, int, const double*, int);  \
-  template int launch_update2_p<S>(dwa_ctx*, void*, void*, const void*, const DevScalars*, bool, \
-                                   int);                                                        \
+                                   DevScalars*, double*, int*, bool, int, const double*, int,   \
+                                   const double*, int);                                         \
+  template int launch_update2_p<S>(dwa_ctx*, void*, void*, const void*, DevScalars*, bool, int, \
+                                   const double*, int);                                         \
   template int norm2_p<S>(dwa_ctx*, const void*, size_t, double*, int*, int);                   \
   template int axpby_p<S>(dwa_ctx*, void*, double, const void*, double, size_t, int,            \
                           const double*);                                                       \

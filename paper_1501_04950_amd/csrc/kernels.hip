@@ -269,7 +269,7 @@ int launch_smix(dwa_ctx* ctx, int prec, int mix, void* out, const void* in, cons
 }
 int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const void* p,
                       const void* q, DevScalars* s, double* partials, int* nblocks, bool adj,
-                      int nrhs, const double* qparts, int nq) {
+                      int nrhs, const double* qparts, int nq, const double* zparts, int nz) {
   if (nrhs > 1 && serial("up1")) {
     const size_t n = field_elems(ctx);
     for (int f = 0; f < nrhs; ++f) {
@@ -277,26 +277,29 @@ int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const v
       int rc = launch_cg_update1(ctx, prec, fshift(x, xacc_prec(prec), n, f), fshift(r, prec, n, f),
                                  fshift(w, prec, n, f), fshift(p, prec, n, f), fshift(q, prec, n, f), s + f,
                                  partials + size_t(f) * ((6 * ctx->Vh + 255) / 256), &nb, adj, 1,
-                                 qparts ? qparts + size_t(f) * nq : nullptr, nq);
+                                 qparts ? qparts + size_t(f) * nq : nullptr, nq,
+                                 zparts ? zparts + size_t(f) * nz : nullptr, nz);
       if (rc) return rc;
       if (nblocks) *nblocks = nb;
     }
     return DWA_OK;
   }
-  DWA_DISPATCH(prec, launch_update1_p<S_>(ctx, x, r, w, p, q, s, partials, nblocks, adj, nrhs, qparts, nq));
+  DWA_DISPATCH(prec, launch_update1_p<S_>(ctx, x, r, w, p, q, s, partials, nblocks, adj, nrhs, qparts, nq,
+                                          zparts, nz));
 }
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
-                      const DevScalars* s, bool adj, int nrhs) {
+                      DevScalars* s, bool adj, int nrhs, const double* zparts, int nz) {
   if (nrhs > 1 && serial("up2")) {
     const size_t n = field_elems(ctx);
     for (int f = 0; f < nrhs; ++f) {
       int rc = launch_cg_update2(ctx, prec, fshift(p, prec, n, f), fshift(u, prec, n, f),
-                                 fshift(z, prec, n, f), s + f, adj, 1);
+                                 fshift(z, prec, n, f), s + f, adj, 1,
+                                 zparts ? zparts + size_t(f) * nz : nullptr, nz);
       if (rc) return rc;
     }
     return DWA_OK;
   }
-  DWA_DISPATCH(prec, launch_update2_p<S_>(ctx, p, u, z, s, adj, nrhs));
+  DWA_DISPATCH(prec, launch_update2_p<S_>(ctx, p, u, z, s, adj, nrhs, zparts, nz));
 }
 int launch_norm2(dwa_ctx* ctx, int prec, const void* x, size_t n, double* partials, int* nblocks,
                  int nrhs) {
