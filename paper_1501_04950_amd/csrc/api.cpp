@@ -562,6 +562,7 @@ struct BatchSys {
   std::vector<int> iters, converged, breakdown;
   long long n_dbb = 0;
   int nb_r = 0;  // partial sums of |r|^2 per field in bank 1 (set by the first half)
+  int nb_z = 0;  // partial sums of |z|^2 per field in bank 2 (set by the second half)
 };
 
 // Called at every host check (k > 0) for each system; last is set at maxiter.
@@ -593,6 +594,8 @@ int batch_freeze(BatchSys& b, int k, hipStream_t st) {
 //   first half:  q = A p, a = gamma / |q|^2, x += a p, r -= a q, |r|^2 partials,
 //                w = premix of r (|r|^2 itself is summed only before a host check)
 //   second half: z = A^dag r, beta = |z|^2 / gamma, p = z + beta p, u = premix of p
+// The scalars come from the partials inside the updates (no finalize launches): update 1
+// sums |q|^2 (bank 0) and gamma = |z|^2 (bank 2), update 2 sums |z|^2 for beta.
 // The graph body is (second half, first half); the first iteration runs its first half
 // eagerly.  A host check after k bodies therefore sees the residual of k updates of x.
 int batch_first_half(BatchSys& b) {
@@ -602,7 +605,7 @@ int batch_first_half(BatchSys& b) {
   DWA_TRY(dbb_from_premix(ctx, b.prec, b.q, b.p, b.u, b.t, bbank(ctx, 0), &nbA, b.nr));
   // a = gamma / |q|^2 per field is summed inside update 1 from the hop's partials
   DWA_TRY(launch_cg_update1(ctx, b.prec, b.x, b.r, b.w, b.p, b.q, sc, bbank(ctx, 1), &nbB, false, b.nr,
-                            bbank(ctx, 0), nbA));
+                            bbank(ctx, 0), nbA, bbank(ctx, 2), b.nb_z));
   b.nb_r = nbB;  // |r|^2 partials: summed into rr only before a host check
   b.n_dbb += b.nr;
   return DWA_OK;
@@ -612,10 +615,9 @@ int batch_second_half(BatchSys& b) {
   dwa_ctx* ctx = b.ctx;
   DevScalars* sc = ctx->batch.d_scal;
   int nbZ = 0;
-  DWA_TRY(dbbdag_from_premix(ctx, b.prec, b.z, b.r, b.w, b.t, bbank(ctx, 0), &nbZ, b.nr));
-  // (rr is not needed here: the next first half recomputes it before any check)
-  DWA_TRY(launch_cg_finalize(ctx, 1, sc, bbank(ctx, 0), nbZ, nullptr, 0, b.nr));
-  DWA_TRY(launch_cg_update2(ctx, b.prec, b.p, b.u, b.z, sc, false, b.nr));
+  DWA_TRY(dbbdag_from_premix(ctx, b.prec, b.z, b.r, b.w, b.t, bbank(ctx, 2), &nbZ, b.nr));
+  b.nb_z = nbZ;
+  DWA_TRY(launch_cg_update2(ctx, b.prec, b.p, b.u, b.z, sc, false, b.nr, bbank(ctx, 2), nbZ));
   b.n_dbb += b.nr;
   return DWA_OK;
 }
@@ -651,9 +653,10 @@ int cgls_multi(std::vector<BatchSys>& S, hipStream_t st, int maxiter, int check_
     DWA_TRY(launch_zero(ctx, xacc_prec(b.prec), b.x, n, b.nr));
     DWA_TRY(launch_axpby(ctx, b.prec, b.r, 1.0, b.rhs, 0.0, n, b.nr));
     DWA_TRY(launch_smix(ctx, b.prec, MIX_G5_IINVT_GINV, b.w, b.r, nullptr, 0.0, ctx->Ls, nullptr, nullptr, b.nr));
-    DWA_TRY(dbbdag_from_premix(ctx, b.prec, b.z, b.r, b.w, b.t, bbank(ctx, 0), &nbA, b.nr));
+    DWA_TRY(dbbdag_from_premix(ctx, b.prec, b.z, b.r, b.w, b.t, bbank(ctx, 2), &nbA, b.nr));
+    b.nb_z = nbA;
     DWA_TRY(launch_norm2(ctx, b.prec, b.rhs, n, bbank(ctx, 1), &nbB, b.nr));
-    DWA_TRY(launch_cg_finalize(ctx, 2, sc, bbank(ctx, 0), nbA, bbank(ctx, 1), nbB, b.nr));
+    DWA_TRY(launch_cg_finalize(ctx, 2, sc, bbank(ctx, 2), nbA, bbank(ctx, 1), nbB, b.nr));
     DWA_TRY(launch_axpby(ctx, b.prec, b.p, 1.0, b.z, 0.0, n, b.nr));
     DWA_TRY(launch_smix(ctx, b.prec, MIX_BG, b.u, b.p, nullptr, 0.0, ctx->Ls, nullptr, nullptr, b.nr));
     b.n_dbb = b.nr;
