@@ -371,7 +371,8 @@ int launch_cg_update1(dwa_ctx* ctx, int prec, void* x, void* r, void* w, const v
 int launch_cg_update2(dwa_ctx* ctx, int prec, void* p, void* u, const void* z,
                       DevScalars* s, bool adj = false, int nrhs = 1, const double* zparts = nullptr,
                       int nz = 0);
-// one block per field: s[r] from partials_a[r * na ...] and partials_b[r * nb ...]
+// one block per field: s[r] from partials_a[r * na ...] and partials_b[r * nb ...];
+// which 2: CG set-up (gamma, rr = b2), which 4: rr for a host check
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* partials_a, int na,
                        const double* partials_b, int nb, int nrhs = 1);
 // gamma *= f for nrhs fields (per-field factors fs[k] when fs is given)

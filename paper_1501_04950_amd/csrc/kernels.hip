@@ -16,10 +16,11 @@ namespace {
 
 constexpr int RED_THREADS = 256;
 
-// which: 0 -> qq, a = gamma/qq ; 1 -> zz (bank a), rr (bank b), beta, gamma ;
-//        2 -> init: gamma = sum(a), rr = b2 = sum(b) ; 3 -> aux = sum(a) ; 4 -> rr = sum(a)
-// Block r finalizes field r of a batch (partials packed per field).  A field whose
-// active flag the host has cleared keeps its x and r (a = 0) and restarts p from z.
+// Scalars of the CG set-up and of the host checks (the per-iteration step lengths a and
+// beta are summed inside the update kernels):
+//   which 2 -> init: gamma = sum(a), rr = b2 = sum(b), flags cleared, field active;
+//   which 4 -> rr = sum(a).
+// Block r finalizes field r of a batch (partials packed per field).
 __global__ void __launch_bounds__(RED_THREADS) cg_finalize_kernel(DevScalars* s, int which,
                                                                    const double* pa, int na,
                                                                    const double* pb, int nb) {
@@ -29,36 +30,12 @@ __global__ void __launch_bounds__(RED_THREADS) cg_finalize_kernel(DevScalars* s,
   const double A = sum_partials_block(pa, na);
   const double B = (pb != nullptr) ? sum_partials_block(pb, nb) : 0.0;
   if (threadIdx.x != 0) return;
-  if (which == 0) {
-    s->qq = A;
-    if (!s->active) {
-      s->a = 0.0;
-    } else if (!(A > 0.0) || !isfinite(A)) {
-      s->flags |= 1;
-      s->a = 0.0;
-    } else {
-      s->a = s->gamma / A;
-    }
-  } else if (which == 1) {
-    s->zz = A;
-    s->rr = B;
-    if (!s->active) {
-      s->beta = 0.0;
-    } else if (!isfinite(A) || !(s->gamma > 0.0)) {
-      s->flags |= 2;
-      s->beta = 0.0;
-    } else {
-      s->beta = A / s->gamma;
-    }
-    s->gamma = A;
-  } else if (which == 2) {
+  if (which == 2) {
     s->gamma = A;
     s->rr = B;
     s->b2 = B;
     s->flags = 0;
     s->active = 1;
-  } else if (which == 3) {
-    s->aux = A;
   } else {
     s->rr = A;
   }
@@ -335,6 +312,10 @@ int launch_convert(dwa_ctx* ctx, int prec_out, void* out, int prec_in, const voi
 
 int launch_cg_finalize(dwa_ctx* ctx, int which, DevScalars* s, const double* pa, int na,
                        const double* pb, int nb, int nrhs) {
+  if (which != 2 && which != 4) {
+    set_error("finalize: unknown scalar set");
+    return DWA_EINVAL;
+  }
   if (nrhs > 1 && serial("fin")) {
     for (int f = 0; f < nrhs; ++f) {
       int rc = launch_cg_finalize(ctx, which, s + f, pa + size_t(f) * na, na,
