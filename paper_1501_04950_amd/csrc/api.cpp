@@ -233,6 +233,21 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
   return DWA_OK;
 }
 
+// rho += -1/2 H chi on the two wall slices of both parities (nr fields field_elems
+// apart): the source chi of D_1(1) P (eta, 0, ..., 0) lives on s = 0 and s = Ls - 1
+// only, so the hop of every other slice would add zeros.
+int wall_hops(dwa_ctx* ctx, void* chi_b, void* chi_r, void* rho_b, void* rho_r, int nr = 1) {
+  const size_t slice = size_t(12) * ctx->Vh;
+  for (const int s : {0, ctx->Ls - 1}) {
+    auto at = [&](void* f) { return static_cast<void*>(static_cast<double2*>(f) + s * slice); };
+    const HopOp hb{at(chi_r), at(rho_b), at(rho_b), nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 0, 1, nullptr, nr};
+    const HopOp hr{at(chi_b), at(rho_r), at(rho_r), nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 1, 1, nullptr, nr};
+    DWA_TRY(launch_hop(ctx, DWA_F64, hb, nullptr));
+    DWA_TRY(launch_hop(ctx, DWA_F64, hr, nullptr));
+  }
+  return DWA_OK;
+}
+
 // |rhs - D_bb x| / |rhs| in FP64 (uses W_Q, W_RES, W_OPB, W_OPR)
 int true_residual64(dwa_ctx* ctx, const void* x, const void* rhs, double rhs_norm, double* rel,
                     void* res_out, bool adj = false) {
@@ -1382,10 +1397,7 @@ int dwa_propagator(dwa_ctx* ctx, void* y1, const void* eta, const dwa_solve_opts
   const int Ls = ctx->Ls;
   // rho = D_1(1) P (eta, 0, ..., 0): wall slices only
   DWA_TRY(launch_source(ctx, W[W_CHI_B], W[W_CHI_R], W[W_RHO_B], W[W_RHO_R], eta));
-  HopOp hb{W[W_CHI_R], W[W_RHO_B], W[W_RHO_B], nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 0, Ls, nullptr};
-  HopOp hr{W[W_CHI_B], W[W_RHO_R], W[W_RHO_R], nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 1, Ls, nullptr};
-  DWA_TRY(launch_hop(ctx, DWA_F64, hb, nullptr));
-  DWA_TRY(launch_hop(ctx, DWA_F64, hr, nullptr));
+  DWA_TRY(wall_hops(ctx, W[W_CHI_B], W[W_CHI_R], W[W_RHO_B], W[W_RHO_R]));
   // phi' = I_bb^-1 (rho_b - D_br I_rr^-1 rho_r) = G^-1 I^-1 (rho_b + 1/2 H_br N rho_r)
   DWA_TRY(launch_smix(ctx, DWA_F64, MIX_N, W[W_T], W[W_RHO_R], nullptr, 0.0, Ls, nullptr, nullptr));
   HopOp prep{W[W_T], W[W_PHI], W[W_RHO_B], nullptr, 0.5, 1.0, 0.0, MIX_GINV_IINV, 0, Ls, nullptr};
@@ -1686,10 +1698,7 @@ int dwa_propagator_multi(dwa_ctx* const* ctxs, int nctx, const int* nrhs, void* 
       for (int f = 0; f < nr; ++f)
         DWA_TRY(launch_source(ctx, at(B_CHI_B, f), at(B_CHI_R, f), at(B_RHO_B, f), at(B_RHO_R, f),
                               static_cast<const double2*>(eta[i]) + f * v12));
-      HopOp hb{w.f64[B_CHI_R], w.f64[B_RHO_B], w.f64[B_RHO_B], nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 0, Ls, nullptr, nr};
-      HopOp hr{w.f64[B_CHI_B], w.f64[B_RHO_R], w.f64[B_RHO_R], nullptr, -0.5, 1.0, 0.0, MIX_IDENTITY, 1, Ls, nullptr, nr};
-      DWA_TRY(launch_hop(ctx, DWA_F64, hb, nullptr));
-      DWA_TRY(launch_hop(ctx, DWA_F64, hr, nullptr));
+      DWA_TRY(wall_hops(ctx, w.f64[B_CHI_B], w.f64[B_CHI_R], w.f64[B_RHO_B], w.f64[B_RHO_R], nr));
       DWA_TRY(launch_smix(ctx, DWA_F64, MIX_N, w.f64[B_T], w.f64[B_RHO_R], nullptr, 0.0, Ls, nullptr, nullptr, nr));
       HopOp prep{w.f64[B_T], w.f64[B_PHI], w.f64[B_RHO_B], nullptr, 0.5, 1.0, 0.0, MIX_GINV_IINV, 0, Ls, nullptr, nr};
       DWA_TRY(launch_hop(ctx, DWA_F64, prep, nullptr));
