@@ -135,8 +135,10 @@ int dwa_destroy(dwa_ctx *ctx);
  * The antiperiodic phase is folded into U_t(t = Lt-1) and FP32/BF16 copies are made. */
 int dwa_set_links(dwa_ctx *ctx, const void *U_dev);
 
-/* Bytes of one half-lattice SoA field of precision prec. */
-size_t dwa_field_bytes(const dwa_ctx *ctx, int prec);
+/* Bytes of nrhs half-lattice SoA fields of precision prec stored back to back (the
+ * batched calls take nrhs fields in one buffer); 0 for a null context, a bad precision
+ * or nrhs < 1. */
+size_t dwa_field_bytes(const dwa_ctx *ctx, int prec, int nrhs);
 /* Number of sites V and slices Ls of the context (either pointer may be NULL). */
 int dwa_get_sizes(const dwa_ctx *ctx, long long *V, int *Ls);
 
@@ -300,6 +302,27 @@ int dwa_propagator_batch(dwa_ctx *ctx, int nrhs, void *y1, const void *eta,
  * context's stream has drained.  stats receives sum(nrhs) entries in context order. */
 int dwa_propagator_multi(dwa_ctx *const *ctxs, int nctx, const int *nrhs, void *const *y1,
                          const void *const *eta, const dwa_solve_opts *opts,
+                         dwa_solve_stats *stats);
+
+/* Batched CGNE at the Schur level (Sec. 3: CG on the normal equation of the red-black
+ * operator D_bb of eq.(redblack); the paper's workload is 12 spin-colour sources per
+ * gauge field, solved together here): solve D_bb x = rhs for nrhs right-hand sides of
+ * each of the nctx contexts (lattices of any size, one device) in one solve.
+ *   rhs_b[i]  device, nrhs FP64 black SoA fields of ctxs[i] back to back
+ *             (dwa_field_bytes(ctxs[i], DWA_F64, nrhs) bytes); read only;
+ *   x_b[i]    device, same layout; receives the solutions (written once, at the end).
+ * Every field runs the CGLS of dwa_cgne_solve from x = 0 (opts->warm_start must be 0);
+ * opts->inner_prec = DWA_F64 runs FP64 CGLS, DWA_F32 / DWA_BF16 low-precision CGLS with
+ * FP64 reliable updates or defect correction (opts->mixed_mode), as in
+ * dwa_propagator_multi.  One hipGraph replays the iteration of all fields between host
+ * checks.  Every context must have reserved at least nrhs fields (dwa_reserve_batch); the
+ * work runs on the first context's batch stream after every context's stream has drained.
+ * stats (host, may be NULL) receives nctx * nrhs entries, context-major; rel_resid is the
+ * FP64 |rhs - D_bb x| / |rhs|.  Returns DWA_ENOCONV if any field missed the tolerance
+ * (all solutions are still written), DWA_EINVAL on a bad argument (before any device
+ * work). */
+int dwa_cgne_solve_batch(dwa_ctx *const *ctxs, int nctx, int nrhs, void *const *x_b,
+                         const void *const *rhs_b, const dwa_solve_opts *opts,
                          dwa_solve_stats *stats);
 
 const char *dwa_strerror(int status);

@@ -15,11 +15,18 @@ import torch
 from . import dwa
 
 
+def _plain(t):
+    """t detached, with any lazy conjugate / negative bit applied to the values, and
+    contiguous: the library reads the memory, not the tensor's flags.  Autograd hands
+    over such views, e.g. the gradient of Re sum(y.conj() * w) is a lazy conjugate."""
+    return t.detach().resolve_conj().resolve_neg().contiguous()
+
+
 class _Propagator(torch.autograd.Function):
     @staticmethod
     def forward(fctx, U, eta, alpha, b, c, holder, opts):
-        holder.set_links(U.detach().contiguous())
-        y1, st, rc = holder.propagator(eta.detach().contiguous(), **opts)
+        holder.set_links(_plain(U))
+        y1, st, rc = holder.propagator(_plain(eta), **opts)
         fctx.holder, fctx.opts = holder, opts
         fctx.save_for_backward(U, eta)
         fctx.stats = st
@@ -31,9 +38,8 @@ class _Propagator(torch.autograd.Function):
         holder = fctx.holder
         need = fctx.needs_input_grad
         want = tuple(k for k, i in (("U", 0), ("eta", 1), ("alpha", 2), ("b", 3), ("c", 4)) if need[i])
-        holder.set_links(U.detach().contiguous())
-        g = holder.propagator_adjoint(eta.detach().contiguous(), gy.detach().contiguous(),
-                                      want=want, **fctx.opts)
+        holder.set_links(_plain(U))
+        g = holder.propagator_adjoint(_plain(eta), _plain(gy), want=want, **fctx.opts)
         dev = eta.device
         out = [None] * 7
         if need[0]:

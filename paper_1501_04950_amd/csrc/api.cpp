@@ -848,6 +848,250 @@ int batch_true_residual(dwa_ctx* ctx, int nr, hipStream_t st, double* res2) {
   return DWA_OK;
 }
 
+// Result of a batched solve of D_bb X = PHI over several contexts (per context, per
+// field): FP64 relative residual of the last recomputation (mixed precision), |PHI|,
+// CG iterations, FP64 residual recomputations, and (FP64 inner solves) whether the
+// recursive residual met the tolerance.
+struct MultiSolve {
+  std::vector<std::vector<double>> rel, bnorm;
+  std::vector<std::vector<int>> iters, outer, fp64_conv;
+};
+
+// Solve D_bb X = PHI (CGNE, Sec. 3) for the nrhs[i] fields held in the batch workspace of
+// every context (B_PHI -> B_X, FP64 black SoA), all on stream st: FP64 CGLS, or
+// low-precision CGLS with FP64 reliable updates or defect correction (opts).
+int multi_solve(dwa_ctx* const* ctxs, int nctx, const int* nrhs, const dwa_solve_opts* o,
+                hipStream_t st, MultiSolve& M) {
+  const int inner = o->inner_prec;
+  auto& rel = M.rel;
+  auto& bnorm = M.bnorm;
+  auto& iters = M.iters;
+  auto& outer = M.outer;
+  auto& fp64_conv = M.fp64_conv;
+  rel.assign(nctx, {});
+  bnorm.assign(nctx, {});
+  iters.assign(nctx, {});
+  outer.assign(nctx, {});
+  fp64_conv.assign(nctx, {});
+  for (int i = 0; i < nctx; ++i) {
+    rel[i].assign(nrhs[i], 1.0);
+    bnorm[i].assign(nrhs[i], 0.0);
+    iters[i].assign(nrhs[i], 0);
+    outer[i].assign(nrhs[i], 0);
+    DWA_TRY(batch_norms(ctxs[i], DWA_F64, ctxs[i]->batch.f64[B_PHI], nrhs[i], st, bnorm[i].data()));
+    for (auto& v : bnorm[i]) v = std::sqrt(v);
+  }
+  if (inner == DWA_F64) {
+    std::vector<BatchSys> S(nctx);
+    for (int i = 0; i < nctx; ++i) {
+      S[i].ctx = ctxs[i];
+      S[i].nr = nrhs[i];
+      S[i].prec = DWA_F64;
+      S[i].x = ctxs[i]->batch.f64[B_X];
+      S[i].rhs = ctxs[i]->batch.f64[B_PHI];
+      S[i].tol.assign(nrhs[i], o->tol);
+      batch_sys_vectors(S[i]);
+    }
+    DWA_TRY(cgls_multi(S, st, o->maxiter, o->check_every, true, BatchHook{}));
+    for (int i = 0; i < nctx; ++i) {
+      iters[i] = S[i].iters;
+      fp64_conv[i] = S[i].converged;
+    }
+  } else if (o->mixed_mode != DWA_MIXED_DEFECT) {
+    // reliable updates: one low-precision CGLS per field for the whole solve, the
+    // scheme of the single-field solver.  At a host check where some field of a
+    // context has reduced its low-precision residual by delta (or is predicted to
+    // have converged), every live field of that context folds x_l into X, gets its
+    // true FP64 residual, and continues from it at unit norm with p and gamma
+    // rescaled.  (One batched FP64 D_bb serves all fields of the context, so they
+    // are updated together.)
+    const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
+    std::vector<std::vector<double>> scale(nctx), rmax(nctx), last(nctx);
+    std::vector<std::vector<int>> stall(nctx);
+    std::vector<BatchSys> S(nctx);
+    for (int i = 0; i < nctx; ++i) {
+      dwa_ctx* ctx = ctxs[i];
+      BatchWs& w = ctx->batch;
+      const int nr = nrhs[i];
+      const size_t n = field_elems(ctx);
+      scale[i] = bnorm[i];
+      rmax[i].assign(nr, 1.0);
+      last[i].assign(nr, 1.0);
+      stall[i].assign(nr, 0);
+      DWA_TRY(launch_zero(ctx, DWA_F64, w.f64[B_X], n, nr));
+      S[i].ctx = ctx;
+      S[i].nr = nr;
+      S[i].prec = inner;
+      S[i].x = w.xacc;
+      S[i].rhs = w.lo[inner][BL_RHS];
+      S[i].tol.assign(nr, 0.0);
+      for (int f = 0; f < nr; ++f) {
+        w.h_coef[f] = bnorm[i][f] > 0.0 ? 1.0 / bnorm[i][f] : 0.0;
+        if (bnorm[i][f] == 0.0) {
+          S[i].tol[f] = -1.0;
+          rel[i][f] = 0.0;
+        }
+      }
+      batch_sys_vectors(S[i]);
+      DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
+      DWA_TRY(launch_convert(ctx, inner, w.lo[inner][BL_RHS], DWA_F64, w.f64[B_PHI], n, 0.0, nr, w.d_coef));
+      // the pinned coefficients are rewritten below only after a synchronisation
+      DWA_HIP(hipStreamSynchronize(st), "coef sync");
+    }
+    const BatchHook hook = [&](BatchSys& b, int k, bool at_end) -> int {
+      const int i = int(&b - S.data());
+      dwa_ctx* ctx = b.ctx;
+      BatchWs& w = ctx->batch;
+      const int nr = b.nr;
+      const size_t n = field_elems(ctx);
+      bool trig = at_end;
+      for (int f = 0; f < nr; ++f) {
+        if (!w.h_active[f]) continue;
+        const double rl = std::sqrt(w.h_scal[f].rr);
+        if (rl <= delta * rmax[i][f] || rl * scale[i][f] / bnorm[i][f] <= 0.5 * o->tol) trig = true;
+      }
+      if (!trig) return DWA_OK;
+      // X += scale x_l (FP64) for the live fields, x_l = 0, true residuals
+      std::vector<int> live(nr);
+      for (int f = 0; f < nr; ++f) {
+        live[f] = w.h_active[f];
+        w.h_coef[f] = live[f] ? scale[i][f] : 0.0;
+      }
+      DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
+      DWA_TRY(launch_fold_acc(ctx, xacc_prec(inner), w.f64[B_X], w.xacc, n, 0.0, nr, w.d_coef));
+      std::vector<double> r2(nr);
+      DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));  // synchronises
+      std::vector<double> fac(nr, 1.0);
+      for (int f = 0; f < nr; ++f) {
+        if (!live[f]) continue;
+        const double r = std::sqrt(r2[f]) / bnorm[i][f];
+        rel[i][f] = r;
+        outer[i][f] += 1;
+        bool stop = false;
+        if (r <= o->tol) {
+          b.converged[f] = 1;
+          stop = true;
+        } else {
+          if (!(r < 0.9 * last[i][f])) stop = ++stall[i][f] >= 3;
+          else stall[i][f] = 0;
+          last[i][f] = r;
+        }
+        if (stop) {
+          b.iters[f] = k;
+          DWA_TRY(batch_freeze(b, f, st));
+          continue;
+        }
+        const double ns = r * bnorm[i][f];
+        fac[f] = scale[i][f] / ns;
+        scale[i][f] = ns;
+        rmax[i][f] = 1.0;
+      }
+      // continue in the new units: p *= fac, gamma *= fac^2, r_l = RES / scale
+      for (int f = 0; f < nr; ++f) {
+        w.h_coef[2 * f] = fac[f];
+        w.h_coef[2 * f + 1] = 0.0;
+        w.h_coef[2 * nr + f] = fac[f] * fac[f];
+        // a zero source has scale 0 (frozen from the start): keep its r at 0
+        w.h_coef[3 * nr + f] = scale[i][f] > 0.0 ? 1.0 / scale[i][f] : 0.0;
+      }
+      DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * 4 * nr, hipMemcpyHostToDevice, st),
+              "coef upload");
+      DWA_TRY(launch_axpby(ctx, inner, b.p, 1.0, b.p, 0.0, n, nr, w.d_coef));
+      DWA_TRY(launch_scale_gamma(ctx, w.d_scal, 1.0, nr, w.d_coef + 2 * nr));
+      DWA_TRY(launch_convert(ctx, inner, b.r, DWA_F64, w.f64[B_RES], n, 0.0, nr, w.d_coef + 3 * nr));
+      DWA_TRY(launch_smix(ctx, inner, MIX_G5_IINVT_GINV, b.w, b.r, nullptr, 0.0, ctx->Ls, nullptr, nullptr, nr));
+      DWA_HIP(hipStreamSynchronize(st), "coef sync");
+      return DWA_OK;
+    };
+    DWA_TRY(cgls_multi(S, st, o->maxiter, o->check_every, true, hook));
+    for (int i = 0; i < nctx; ++i) iters[i] = S[i].iters;
+  } else {
+    // defect correction: FP64 residuals, one batched low-precision CGLS per round
+    const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
+    std::vector<std::vector<int>> stall(nctx);
+    std::vector<std::vector<double>> prev(nctx);
+    for (int i = 0; i < nctx; ++i) {
+      BatchWs& w = ctxs[i]->batch;
+      const size_t n = field_elems(ctxs[i]);
+      DWA_TRY(launch_zero(ctxs[i], DWA_F64, w.f64[B_X], n, nrhs[i]));
+      DWA_TRY(launch_axpby(ctxs[i], DWA_F64, w.f64[B_RES], 1.0, w.f64[B_PHI], 0.0, n, nrhs[i]));
+      stall[i].assign(nrhs[i], 0);
+      prev[i].assign(nrhs[i], 1.0);
+      for (int f = 0; f < nrhs[i]; ++f)
+        if (bnorm[i][f] == 0.0) rel[i][f] = 0.0;
+    }
+    int total = 0;
+    for (;;) {
+      // one batched low-precision CGLS over the contexts that still have live fields
+      std::vector<BatchSys> S;
+      std::vector<int> which;
+      for (int i = 0; i < nctx; ++i) {
+        dwa_ctx* ctx = ctxs[i];
+        BatchWs& w = ctx->batch;
+        const int nr = nrhs[i];
+        const size_t n = field_elems(ctx);
+        BatchSys b;
+        b.ctx = ctx;
+        b.nr = nr;
+        b.prec = inner;
+        b.x = w.xacc;
+        b.rhs = w.lo[inner][BL_RHS];
+        b.tol.assign(nr, -1.0);
+        batch_sys_vectors(b);
+        bool live_any = false;
+        for (int f = 0; f < nr; ++f) {
+          const bool live = rel[i][f] > o->tol && stall[i][f] < 3;
+          w.h_coef[f] = live ? 1.0 / (rel[i][f] * bnorm[i][f]) : 0.0;
+          if (live) {
+            b.tol[f] = std::max(delta, 0.5 * o->tol / rel[i][f]);
+            live_any = true;
+          }
+        }
+        if (!live_any) continue;
+        // right-hand sides r / |r| in the inner storage precision
+        DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
+        DWA_TRY(launch_convert(ctx, inner, w.lo[inner][BL_RHS], DWA_F64, w.f64[B_RES], n, 0.0, nr, w.d_coef));
+        S.push_back(std::move(b));
+        which.push_back(i);
+      }
+      if (S.empty() || total >= o->maxiter) break;
+      DWA_TRY(cgls_multi(S, st, o->maxiter - total, o->check_every, true, BatchHook{}));
+      int round_max = 0;
+      for (size_t j = 0; j < S.size(); ++j) {
+        const int i = which[j];
+        dwa_ctx* ctx = ctxs[i];
+        BatchWs& w = ctx->batch;
+        const int nr = nrhs[i];
+        const size_t n = field_elems(ctx);
+        for (int f = 0; f < nr; ++f) {
+          const bool live = S[j].tol[f] >= 0.0;
+          w.h_coef[f] = live ? rel[i][f] * bnorm[i][f] : 0.0;
+          if (live) {
+            iters[i][f] += S[j].iters[f];
+            outer[i][f] += 1;
+            round_max = std::max(round_max, S[j].iters[f]);
+          }
+        }
+        // X += |r| e in FP64, then the new residuals
+        DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
+        DWA_TRY(launch_fold_acc(ctx, xacc_prec(inner), w.f64[B_X], w.xacc, n, 0.0, nr, w.d_coef));
+        std::vector<double> r2(nr);
+        DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));
+        for (int f = 0; f < nr; ++f) {
+          if (S[j].tol[f] < 0.0) continue;
+          const double r = bnorm[i][f] > 0.0 ? std::sqrt(r2[f]) / bnorm[i][f] : 0.0;
+          if (!(r < 0.9 * prev[i][f])) stall[i][f] += 1;
+          else stall[i][f] = 0;
+          prev[i][f] = r;
+          rel[i][f] = r;
+        }
+      }
+      total += std::max(round_max, 1);
+    }
+  }
+  return DWA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1079,9 +1323,9 @@ int dwa_set_links(dwa_ctx* ctx, const void* U) {
   return DWA_OK;
 }
 
-size_t dwa_field_bytes(const dwa_ctx* ctx, int prec) {
-  if (!ctx || !valid_prec(prec)) return 0;
-  return elem_bytes(prec) * field_elems(ctx);
+size_t dwa_field_bytes(const dwa_ctx* ctx, int prec, int nrhs) {
+  if (!ctx || !valid_prec(prec) || nrhs < 1) return 0;
+  return elem_bytes(prec) * field_elems(ctx) * size_t(nrhs);
 }
 
 int dwa_get_sizes(const dwa_ctx* ctx, long long* V, int* Ls) {
@@ -1705,224 +1949,12 @@ int dwa_propagator_multi(dwa_ctx* const* ctxs, int nctx, const int* nrhs, void* 
     }
     // solve D_bb X = PHI for every field
     const int inner = o->inner_prec;
-    std::vector<std::vector<double>> rel(nctx), bnorm(nctx);
-    std::vector<std::vector<int>> iters(nctx), outer(nctx), fp64_conv(nctx);
-    for (int i = 0; i < nctx; ++i) {
-      rel[i].assign(nrhs[i], 1.0);
-      bnorm[i].assign(nrhs[i], 0.0);
-      iters[i].assign(nrhs[i], 0);
-      outer[i].assign(nrhs[i], 0);
-      DWA_TRY(batch_norms(ctxs[i], DWA_F64, ctxs[i]->batch.f64[B_PHI], nrhs[i], st, bnorm[i].data()));
-      for (auto& v : bnorm[i]) v = std::sqrt(v);
-    }
-    if (inner == DWA_F64) {
-      std::vector<BatchSys> S(nctx);
-      for (int i = 0; i < nctx; ++i) {
-        S[i].ctx = ctxs[i];
-        S[i].nr = nrhs[i];
-        S[i].prec = DWA_F64;
-        S[i].x = ctxs[i]->batch.f64[B_X];
-        S[i].rhs = ctxs[i]->batch.f64[B_PHI];
-        S[i].tol.assign(nrhs[i], o->tol);
-        batch_sys_vectors(S[i]);
-      }
-      DWA_TRY(cgls_multi(S, st, o->maxiter, o->check_every, true, BatchHook{}));
-      for (int i = 0; i < nctx; ++i) {
-        iters[i] = S[i].iters;
-        fp64_conv[i] = S[i].converged;
-      }
-    } else if (o->mixed_mode != DWA_MIXED_DEFECT) {
-      // reliable updates: one low-precision CGLS per field for the whole solve, the
-      // scheme of the single-field solver.  At a host check where some field of a
-      // context has reduced its low-precision residual by delta (or is predicted to
-      // have converged), every live field of that context folds x_l into X, gets its
-      // true FP64 residual, and continues from it at unit norm with p and gamma
-      // rescaled.  (One batched FP64 D_bb serves all fields of the context, so they
-      // are updated together.)
-      const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
-      std::vector<std::vector<double>> scale(nctx), rmax(nctx), last(nctx);
-      std::vector<std::vector<int>> stall(nctx);
-      std::vector<BatchSys> S(nctx);
-      for (int i = 0; i < nctx; ++i) {
-        dwa_ctx* ctx = ctxs[i];
-        BatchWs& w = ctx->batch;
-        const int nr = nrhs[i];
-        const size_t n = field_elems(ctx);
-        scale[i] = bnorm[i];
-        rmax[i].assign(nr, 1.0);
-        last[i].assign(nr, 1.0);
-        stall[i].assign(nr, 0);
-        DWA_TRY(launch_zero(ctx, DWA_F64, w.f64[B_X], n, nr));
-        S[i].ctx = ctx;
-        S[i].nr = nr;
-        S[i].prec = inner;
-        S[i].x = w.xacc;
-        S[i].rhs = w.lo[inner][BL_RHS];
-        S[i].tol.assign(nr, 0.0);
-        for (int f = 0; f < nr; ++f) {
-          w.h_coef[f] = bnorm[i][f] > 0.0 ? 1.0 / bnorm[i][f] : 0.0;
-          if (bnorm[i][f] == 0.0) {
-            S[i].tol[f] = -1.0;
-            rel[i][f] = 0.0;
-          }
-        }
-        batch_sys_vectors(S[i]);
-        DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
-        DWA_TRY(launch_convert(ctx, inner, w.lo[inner][BL_RHS], DWA_F64, w.f64[B_PHI], n, 0.0, nr, w.d_coef));
-        // the pinned coefficients are rewritten below only after a synchronisation
-        DWA_HIP(hipStreamSynchronize(st), "coef sync");
-      }
-      const BatchHook hook = [&](BatchSys& b, int k, bool at_end) -> int {
-        const int i = int(&b - S.data());
-        dwa_ctx* ctx = b.ctx;
-        BatchWs& w = ctx->batch;
-        const int nr = b.nr;
-        const size_t n = field_elems(ctx);
-        bool trig = at_end;
-        for (int f = 0; f < nr; ++f) {
-          if (!w.h_active[f]) continue;
-          const double rl = std::sqrt(w.h_scal[f].rr);
-          if (rl <= delta * rmax[i][f] || rl * scale[i][f] / bnorm[i][f] <= 0.5 * o->tol) trig = true;
-        }
-        if (!trig) return DWA_OK;
-        // X += scale x_l (FP64) for the live fields, x_l = 0, true residuals
-        std::vector<int> live(nr);
-        for (int f = 0; f < nr; ++f) {
-          live[f] = w.h_active[f];
-          w.h_coef[f] = live[f] ? scale[i][f] : 0.0;
-        }
-        DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
-        DWA_TRY(launch_fold_acc(ctx, xacc_prec(inner), w.f64[B_X], w.xacc, n, 0.0, nr, w.d_coef));
-        std::vector<double> r2(nr);
-        DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));  // synchronises
-        std::vector<double> fac(nr, 1.0);
-        for (int f = 0; f < nr; ++f) {
-          if (!live[f]) continue;
-          const double r = std::sqrt(r2[f]) / bnorm[i][f];
-          rel[i][f] = r;
-          outer[i][f] += 1;
-          bool stop = false;
-          if (r <= o->tol) {
-            b.converged[f] = 1;
-            stop = true;
-          } else {
-            if (!(r < 0.9 * last[i][f])) stop = ++stall[i][f] >= 3;
-            else stall[i][f] = 0;
-            last[i][f] = r;
-          }
-          if (stop) {
-            b.iters[f] = k;
-            DWA_TRY(batch_freeze(b, f, st));
-            continue;
-          }
-          const double ns = r * bnorm[i][f];
-          fac[f] = scale[i][f] / ns;
-          scale[i][f] = ns;
-          rmax[i][f] = 1.0;
-        }
-        // continue in the new units: p *= fac, gamma *= fac^2, r_l = RES / scale
-        for (int f = 0; f < nr; ++f) {
-          w.h_coef[2 * f] = fac[f];
-          w.h_coef[2 * f + 1] = 0.0;
-          w.h_coef[2 * nr + f] = fac[f] * fac[f];
-          // a zero source has scale 0 (frozen from the start): keep its r at 0
-          w.h_coef[3 * nr + f] = scale[i][f] > 0.0 ? 1.0 / scale[i][f] : 0.0;
-        }
-        DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * 4 * nr, hipMemcpyHostToDevice, st),
-                "coef upload");
-        DWA_TRY(launch_axpby(ctx, inner, b.p, 1.0, b.p, 0.0, n, nr, w.d_coef));
-        DWA_TRY(launch_scale_gamma(ctx, w.d_scal, 1.0, nr, w.d_coef + 2 * nr));
-        DWA_TRY(launch_convert(ctx, inner, b.r, DWA_F64, w.f64[B_RES], n, 0.0, nr, w.d_coef + 3 * nr));
-        DWA_TRY(launch_smix(ctx, inner, MIX_G5_IINVT_GINV, b.w, b.r, nullptr, 0.0, ctx->Ls, nullptr, nullptr, nr));
-        DWA_HIP(hipStreamSynchronize(st), "coef sync");
-        return DWA_OK;
-      };
-      DWA_TRY(cgls_multi(S, st, o->maxiter, o->check_every, true, hook));
-      for (int i = 0; i < nctx; ++i) iters[i] = S[i].iters;
-    } else {
-      // defect correction: FP64 residuals, one batched low-precision CGLS per round
-      const double delta = (o->delta > 0.0 && o->delta < 1.0) ? o->delta : 0.1;
-      std::vector<std::vector<int>> stall(nctx);
-      std::vector<std::vector<double>> prev(nctx);
-      for (int i = 0; i < nctx; ++i) {
-        BatchWs& w = ctxs[i]->batch;
-        const size_t n = field_elems(ctxs[i]);
-        DWA_TRY(launch_zero(ctxs[i], DWA_F64, w.f64[B_X], n, nrhs[i]));
-        DWA_TRY(launch_axpby(ctxs[i], DWA_F64, w.f64[B_RES], 1.0, w.f64[B_PHI], 0.0, n, nrhs[i]));
-        stall[i].assign(nrhs[i], 0);
-        prev[i].assign(nrhs[i], 1.0);
-        for (int f = 0; f < nrhs[i]; ++f)
-          if (bnorm[i][f] == 0.0) rel[i][f] = 0.0;
-      }
-      int total = 0;
-      for (;;) {
-        // one batched low-precision CGLS over the contexts that still have live fields
-        std::vector<BatchSys> S;
-        std::vector<int> which;
-        for (int i = 0; i < nctx; ++i) {
-          dwa_ctx* ctx = ctxs[i];
-          BatchWs& w = ctx->batch;
-          const int nr = nrhs[i];
-          const size_t n = field_elems(ctx);
-          BatchSys b;
-          b.ctx = ctx;
-          b.nr = nr;
-          b.prec = inner;
-          b.x = w.xacc;
-          b.rhs = w.lo[inner][BL_RHS];
-          b.tol.assign(nr, -1.0);
-          batch_sys_vectors(b);
-          bool live_any = false;
-          for (int f = 0; f < nr; ++f) {
-            const bool live = rel[i][f] > o->tol && stall[i][f] < 3;
-            w.h_coef[f] = live ? 1.0 / (rel[i][f] * bnorm[i][f]) : 0.0;
-            if (live) {
-              b.tol[f] = std::max(delta, 0.5 * o->tol / rel[i][f]);
-              live_any = true;
-            }
-          }
-          if (!live_any) continue;
-          // right-hand sides r / |r| in the inner storage precision
-          DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
-          DWA_TRY(launch_convert(ctx, inner, w.lo[inner][BL_RHS], DWA_F64, w.f64[B_RES], n, 0.0, nr, w.d_coef));
-          S.push_back(std::move(b));
-          which.push_back(i);
-        }
-        if (S.empty() || total >= o->maxiter) break;
-        DWA_TRY(cgls_multi(S, st, o->maxiter - total, o->check_every, true, BatchHook{}));
-        int round_max = 0;
-        for (size_t j = 0; j < S.size(); ++j) {
-          const int i = which[j];
-          dwa_ctx* ctx = ctxs[i];
-          BatchWs& w = ctx->batch;
-          const int nr = nrhs[i];
-          const size_t n = field_elems(ctx);
-          for (int f = 0; f < nr; ++f) {
-            const bool live = S[j].tol[f] >= 0.0;
-            w.h_coef[f] = live ? rel[i][f] * bnorm[i][f] : 0.0;
-            if (live) {
-              iters[i][f] += S[j].iters[f];
-              outer[i][f] += 1;
-              round_max = std::max(round_max, S[j].iters[f]);
-            }
-          }
-          // X += |r| e in FP64, then the new residuals
-          DWA_HIP(hipMemcpyAsync(w.d_coef, w.h_coef, sizeof(double) * nr, hipMemcpyHostToDevice, st), "coef upload");
-          DWA_TRY(launch_fold_acc(ctx, xacc_prec(inner), w.f64[B_X], w.xacc, n, 0.0, nr, w.d_coef));
-          std::vector<double> r2(nr);
-          DWA_TRY(batch_true_residual(ctx, nr, st, r2.data()));
-          for (int f = 0; f < nr; ++f) {
-            if (S[j].tol[f] < 0.0) continue;
-            const double r = bnorm[i][f] > 0.0 ? std::sqrt(r2[f]) / bnorm[i][f] : 0.0;
-            if (!(r < 0.9 * prev[i][f])) stall[i][f] += 1;
-            else stall[i][f] = 0;
-            prev[i][f] = r;
-            rel[i][f] = r;
-          }
-        }
-        total += std::max(round_max, 1);
-      }
-    }
+    MultiSolve M;
+    DWA_TRY(multi_solve(ctxs, nctx, nrhs, o, st, M));
+    const auto& iters = M.iters;
+    const auto& outer = M.outer;
+    const auto& bnorm = M.bnorm;
+    const auto& fp64_conv = M.fp64_conv;
     // final residuals, reconstruction and extraction
     int status = DWA_OK;
     size_t off = 0;
@@ -1978,6 +2010,75 @@ int dwa_propagator_batch(dwa_ctx* ctx, int nrhs, void* y1, const void* eta, cons
   const void* const e[1] = {eta};
   if (!ctx) return einval("null context");
   return dwa_propagator_multi(c, 1, n, y, e, o, stats);
+}
+
+int dwa_cgne_solve_batch(dwa_ctx* const* ctxs, int nctx, int nrhs, void* const* x_b,
+                         const void* const* rhs_b, const dwa_solve_opts* o, dwa_solve_stats* stats) {
+  if (!ctxs || nctx < 1 || nrhs < 1 || !x_b || !rhs_b || !o)
+    return einval("null argument, nctx < 1 or nrhs < 1");
+  if (!(o->tol > 0.0) || o->maxiter < 0) return einval("bad tolerance or maxiter");
+  if (!valid_prec(o->inner_prec)) return einval("bad inner precision");
+  if (o->mixed_mode != DWA_MIXED_RELIABLE && o->mixed_mode != DWA_MIXED_DEFECT)
+    return einval("bad mixed_mode");
+  if (o->warm_start) return einval("batched CGNE starts from x = 0 (warm_start must be 0)");
+  for (int i = 0; i < nctx; ++i) {
+    DWA_TRY(check_ctx(ctxs[i]));
+    if (nrhs > ctxs[i]->batch.nmax) return einval("batch larger than reserved (dwa_reserve_batch)");
+    if (!x_b[i] || !rhs_b[i]) return einval("null field");
+    if (ctxs[i]->device != ctxs[0]->device) return einval("contexts on different devices");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return einval("a context appears twice");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = ctxs[0]->batch.stream;
+  std::vector<hipStream_t> saved(nctx);
+  for (int i = 0; i < nctx; ++i) {
+    DWA_HIP(hipStreamSynchronize(ctxs[i]->stream), "batch entry sync");
+    saved[i] = ctxs[i]->stream;
+    ctxs[i]->stream = st;
+  }
+  std::vector<int> nr(nctx, nrhs);
+  auto run = [&]() -> int {
+    // the right-hand sides into the batch workspace (the solve reads PHI, writes X)
+    for (int i = 0; i < nctx; ++i)
+      DWA_HIP(hipMemcpyAsync(ctxs[i]->batch.f64[B_PHI], rhs_b[i], dwa_field_bytes(ctxs[i], DWA_F64, nrhs),
+                             hipMemcpyDeviceToDevice, st),
+              "rhs copy");
+    MultiSolve M;
+    DWA_TRY(multi_solve(ctxs, nctx, nr.data(), o, st, M));
+    int status = DWA_OK;
+    for (int i = 0; i < nctx; ++i) {
+      std::vector<double> r2(nrhs);
+      DWA_TRY(batch_true_residual(ctxs[i], nrhs, st, r2.data()));
+      DWA_HIP(hipMemcpyAsync(x_b[i], ctxs[i]->batch.f64[B_X], dwa_field_bytes(ctxs[i], DWA_F64, nrhs),
+                             hipMemcpyDeviceToDevice, st),
+              "solution copy");
+      for (int f = 0; f < nrhs; ++f) {
+        const double b = M.bnorm[i][f];
+        const double r = b > 0.0 ? std::sqrt(r2[f]) / b : 0.0;
+        const bool conv = o->inner_prec == DWA_F64 ? M.fp64_conv[i][f] != 0 : r <= o->tol;
+        if (!conv) status = DWA_ENOCONV;
+        if (stats) {
+          dwa_solve_stats& sf = stats[size_t(i) * nrhs + f];
+          sf = dwa_solve_stats{};
+          sf.iters = M.iters[i][f];
+          sf.outer = M.outer[i][f];
+          sf.converged = conv;
+          sf.rel_resid = r;
+        }
+      }
+    }
+    DWA_HIP(hipStreamSynchronize(st), "batch sync");
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats)
+      for (size_t k = 0; k < size_t(nctx) * nrhs; ++k) stats[k].time_ms = ms;
+    return status;
+  };
+  const int status = run();
+  if (status != DWA_OK && status != DWA_ENOCONV) (void)hipStreamSynchronize(st);
+  for (int i = 0; i < nctx; ++i) ctxs[i]->stream = saved[i];
+  if (status == DWA_ENOCONV) set_error("some field of the batch did not converge");
+  return status;
 }
 
 // Host-only access to the site-local matrices (no device needed); used to check

@@ -96,7 +96,7 @@ def lib():
         "dwa_create": (c_int, [POINTER(c_void_p), POINTER(dwa_params), P]),
         "dwa_destroy": (c_int, [P]),
         "dwa_set_links": (c_int, [P, P]),
-        "dwa_field_bytes": (c_size_t, [P, c_int]),
+        "dwa_field_bytes": (c_size_t, [P, c_int, c_int]),
         "dwa_get_sizes": (c_int, [P, POINTER(c_longlong), POINTER(c_int)]),
         "dwa_pack_spinor5": (c_int, [P, c_int, P, P, c_int]),
         "dwa_unpack_spinor5": (c_int, [P, c_int, P, P, c_int]),
@@ -117,6 +117,9 @@ def lib():
         "dwa_propagator_batch": (c_int, [P, c_int, P, P, POINTER(dwa_solve_opts),
                                          POINTER(dwa_solve_stats)]),
         "dwa_propagator_multi": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int), POINTER(c_void_p),
+                                         POINTER(c_void_p), POINTER(dwa_solve_opts),
+                                         POINTER(dwa_solve_stats)]),
+        "dwa_cgne_solve_batch": (c_int, [POINTER(c_void_p), c_int, c_int, POINTER(c_void_p),
                                          POINTER(c_void_p), POINTER(dwa_solve_opts),
                                          POINTER(dwa_solve_stats)]),
         "dwa_autotune": (c_int, [P, c_int, c_int, POINTER(dwa_tune_entry), c_int, POINTER(c_int)]),
@@ -183,6 +186,16 @@ def _ptr(t):
     return c_void_p(t.data_ptr())
 
 
+def check_storage(t):
+    """Reject tensors whose storage does not hold their values: a lazily conjugated or
+    negated view (``x.conj()``, ``-x`` of a conjugate) keeps the unconjugated numbers in
+    memory and a flag on the tensor, and the library reads memory.  Resolve such views
+    first (``t.resolve_conj().resolve_neg()``)."""
+    if t.is_conj() or t.is_neg():
+        raise ValueError("tensor is a lazy conjugate or negative view; call resolve_conj() / "
+                         "resolve_neg() before passing it to the library")
+
+
 class Context:
     """One lattice, parameter set and gauge field on the current GPU (dwa_create)."""
 
@@ -212,6 +225,11 @@ class Context:
             pass
 
     # -- fields -------------------------------------------------------------
+    def field_bytes(self, prec="f64", nrhs=1):
+        """Bytes of nrhs half fields of precision prec (dwa_field_bytes)."""
+        p = PREC[prec] if isinstance(prec, str) else int(prec)
+        return int(lib().dwa_field_bytes(self._h, p, int(nrhs)))
+
     def half_field(self, prec="f64", zero=True):
         torch = _torch()
         p = PREC[prec] if isinstance(prec, str) else prec
@@ -230,6 +248,7 @@ class Context:
         n = self.Ls * 12 * self.Vh * (2 if p == DWA_BF16 else 1)
         if t.dtype != want or not t.is_contiguous() or t.numel() != n or t.device != self.device:
             raise ValueError(f"half field must be a contiguous {want} tensor of {n} elements on {self.device}")
+        check_storage(t)
         return p
 
     def _check_canon(self, t, shape):
@@ -237,6 +256,7 @@ class Context:
         if (t.dtype != torch.complex128 or not t.is_contiguous() or tuple(t.shape) != tuple(shape)
                 or t.device != self.device):
             raise ValueError(f"expected contiguous complex128 {tuple(shape)} on {self.device}")
+        check_storage(t)
 
     def set_links(self, U):
         self._check_canon(U, (4, self.V, 3, 3))
@@ -488,3 +508,31 @@ def propagator_multi(batches, **kw):
         out.append([st[k + j].as_dict() for j in range(nr[i])])
         k += nr[i]
     return ys, out, rc
+
+
+def cgne_solve_batch(batches, **kw):
+    """Batched Schur-level CGNE over several contexts (dwa_cgne_solve_batch): D_bb x = rhs
+    for every right-hand side.  batches: list of (Context, rhs [n, Ls, 12, Vh] complex128
+    black half fields), the same n for every context.  Returns (list of x batches, list of
+    per-context stats lists, status)."""
+    torch = _torch()
+    nctx = len(batches)
+    if nctx < 1:
+        raise ValueError("no batches")
+    n = int(batches[0][1].shape[0])
+    ctxs = (c_void_p * nctx)()
+    xs, rhss = [], []
+    for i, (ctx, rhs) in enumerate(batches):
+        if rhs.dim() != 4 or int(rhs.shape[0]) != n or not rhs.is_contiguous():
+            raise ValueError("rhs must be a contiguous [n, Ls, 12, Vh] batch, the same n everywhere")
+        ctx._check_half(rhs[0], "f64")
+        check_storage(rhs)
+        ctxs[i] = ctx._h.value
+        xs.append(torch.zeros_like(rhs))
+        rhss.append(rhs)
+    xp = (c_void_p * nctx)(*[x.data_ptr() for x in xs])
+    rp = (c_void_p * nctx)(*[r.data_ptr() for r in rhss])
+    o = Context.opts(**kw)
+    st = (dwa_solve_stats * (nctx * n))()
+    rc = check(lib().dwa_cgne_solve_batch(ctxs, nctx, n, xp, rp, byref(o), st), allow=(DWA_ENOCONV,))
+    return xs, [[st[i * n + j].as_dict() for j in range(n)] for i in range(nctx)], rc

@@ -66,13 +66,14 @@ def test_calls_reject_null_context():
     assert L.dwa_reserve_batch(None, 4) == dwa.DWA_EINVAL
     assert L.dwa_propagator_batch(None, 1, None, None, None, None) == dwa.DWA_EINVAL
     assert L.dwa_propagator_multi(None, 0, None, None, None, None, None) == dwa.DWA_EINVAL
+    assert L.dwa_cgne_solve_batch(None, 0, 1, None, None, None, None) == dwa.DWA_EINVAL
     assert L.dwa_apply_Dbb(None, 0, None, None) == dwa.DWA_EINVAL
     assert L.dwa_set_links(None, None) == dwa.DWA_EINVAL
     assert L.dwa_propagator(None, None, None, None, None, None) == dwa.DWA_EINVAL
     assert L.dwa_autotune(None, 0, 1, None, 0, None) == dwa.DWA_EINVAL
     assert L.dwa_set_tuning(None, 0, 16, 0, 1, 0) == dwa.DWA_EINVAL
     assert L.dwa_get_tuning(None, 0, None, None, None, None) == dwa.DWA_EINVAL
-    assert L.dwa_field_bytes(None, 0) == 0
+    assert L.dwa_field_bytes(None, 0, 1) == 0
     assert L.dwa_strerror(dwa.DWA_ENOCONV).decode() == "solver did not converge"
 
 

@@ -203,6 +203,27 @@ def test_autograd_function(c5):
     _close(fd, adj, float(L2))
 
 
+def test_autograd_lazy_conjugate_gradient(c5):
+    """L = Re sum(conj(y_1) * eta') is the same loss as Re <eta', y_1>, but autograd hands
+    the backward a lazily conjugated gradient of y_1 (the value lives in memory
+    conjugated, with a flag on the tensor).  The backward must resolve it: its gradients
+    equal the library's adjoint gradients of Re <eta', y_1>.  The forward inputs may be
+    such views as well (eta passed as conj(conj(eta)))."""
+    from paper_1501_04950_amd import autograd as dag
+    ctx, g = c5["ctx"], c5["g"]
+    U = c5["Ud"].clone().requires_grad_(True)
+    eta = c5["eta"].clone().requires_grad_(True)
+    y = dag.propagator(ctx, U, eta.conj().conj(), tol=1e-13, check_every=5)
+    L = torch.sum(torch.conj(y) * c5["eta_p"]).real
+    L.backward()
+    say(f"    L {float(L):.12e} library {g['L']:.12e}")
+    assert abs(float(L) - g["L"]) <= 1e-10 * abs(g["L"])
+    assert rel(U.grad.cpu().numpy(), g["U"].cpu().numpy()) < 1e-10
+    assert rel(eta.grad.cpu().numpy(), g["eta"].cpu().numpy()) < 1e-10
+    with pytest.raises(ValueError):
+        ctx.propagator(c5["eta"].conj(), tol=1e-6)
+
+
 @pytest.mark.parametrize("inner,delta", [("f32", 0.05), ("bf16", 0.3)])
 def test_c5_mixed_precision_gradients(c5, inner, delta):
     """Both solves in FP32 or BF16 storage with FP64 reliable updates (tol 1e-10): the
