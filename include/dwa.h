@@ -159,6 +159,19 @@ int dwa_apply_Dw(dwa_ctx *ctx, void *out, const void *in, int nslices);
 int dwa_apply_Dbb(dwa_ctx *ctx, int prec, void *out_b, const void *in_b);
 int dwa_apply_Dbb_dag(dwa_ctx *ctx, int prec, void *out_b, const void *in_b);
 
+/* dwa_apply_Dbb for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same operator and
+ * kernels, bitwise the same result, but its two intermediate half fields (B G in, black,
+ * and the first hop's output, red) live in a static 64 MiB device array of the library
+ * (one per GPU, set up by dwa_create and held until the process ends) instead of the
+ * context's workspace.  The call allocates nothing.  Limit: the two fields, each rounded up
+ * to 256 bytes, must fit in 64 MiB (FP64 at 8^3 x 16, L_s = 12 takes 18.9 MB; BF16 at
+ * 16^3 x 32, L_s = 16 takes 101 MB and is rejected); larger lattices return DWA_EINVAL.
+ * Every call on one GPU uses that GPU's array, so calls that overlap in time on one GPU
+ * (other threads, other streams, other contexts) race: serialise them.  Nothing in the
+ * array has to start at zero (both fields are written in full before they are read). */
+int dwa_apply_Dbb_static(dwa_ctx *ctx, int prec, void *out_b, const void *in_b);
+
 /* One launch of the fused hop kernel: out = M_kind (H in), where H is the hopping sum
  * of eq.(wilson) without its -1/2, taken from the parity 1 - parity_out to parity_out
  * on every slice, and M_kind is a fifth-dimension matrix of dwa_debug_smatrix (kinds

@@ -1156,6 +1156,7 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
   };
   int rc = hip_fail(hipGetDevice(&ctx->device), "hipGetDevice");
   if (rc) return fail(rc);
+  if ((rc = scratch_init(ctx->device))) return fail(rc);
 
   // geometry: checkerboard <-> lexicographic and neighbour tables
   const int Lx = p->dims[0], Ly = p->dims[1], Lz = p->dims[2], Lt = p->dims[3];

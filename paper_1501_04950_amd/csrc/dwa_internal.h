@@ -413,5 +413,9 @@ template <typename SO, typename SI> int convert_p(dwa_ctx*, void*, const void*, 
 size_t field_elems(const dwa_ctx* ctx);  // Ls * 12 * Vh complex numbers
 void set_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
+// the static scratch of dwa_apply_Dbb_static (scratch.hip): per-device address lookup
+// (once per device, with that device current) and its size
+int scratch_init(int device);
+size_t scratch_bytes();
 
 }  // namespace dwa

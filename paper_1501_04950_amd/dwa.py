@@ -103,6 +103,7 @@ def lib():
         "dwa_apply_Dw": (c_int, [P, P, P, c_int]),
         "dwa_apply_Dbb": (c_int, [P, c_int, P, P]),
         "dwa_apply_Dbb_dag": (c_int, [P, c_int, P, P]),
+        "dwa_apply_Dbb_static": (c_int, [P, c_int, P, P]),
         "dwa_apply_hop": (c_int, [P, c_int, c_int, c_int, P, P]),
         "dwa_cgne_solve": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats)]),
         "dwa_propagator": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats), P]),
