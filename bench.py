@@ -52,6 +52,8 @@ def parse():
                     help="keep the default hop tiles instead of running the autotuner")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched 3-lattice x 12-source solve")
+    ap.add_argument("--no-zolo", action="store_true",
+                    help="skip the Zolotarev-coefficient study")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 4^4 and 8^3x16 time-to-solution runs")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -277,6 +279,11 @@ def main():
     if not args.no_batch:
         batch = batch_bench(torch, dwa, synth, dev, stream, args)
 
+    # --- Zolotarev coefficients with the concave ordering, and their alpha sweep -------
+    zolo = None
+    if not args.no_zolo:
+        zolo = zolotarev_study(torch, dwa, Ud, w, args)
+
     # --- the small workloads (launch-latency bound): time to solution ----------------
     small = None
     if not args.no_small:
@@ -321,6 +328,7 @@ def main():
         "roofline": roofline,
         "tuning": tuning,
         "small_workloads": small,
+        "zolotarev": zolo,
         "gradients": grad,
         "alpha_sweep": sweep,
         "batch": batch,
@@ -600,6 +608,63 @@ def cpu_baseline(U, dims, Ls, w, alpha, fp64, c1_gpu, dbb_reps=3):
             "c3_solve_estimate": {"value_s": round(est, 1) if est else None, "estimate": True,
                                   "how": f"oracle D_bb median x {n_dbb} D_bb applications of the GPU "
                                          "FP64 solve of the same system (not a timed solve)"}}
+
+
+def zolotarev_study(torch, dwa, Ud, w, args, Ls=10, m=0.06, steps=300):
+    """The Zolotarev row of the paper's table (m = 0.06, Ls = 10) on the paper-shaped
+    field: spectral bounds of |gamma_5 D_w| by Lanczos on the GPU, Zolotarev coefficients
+    b_i = c_i = omega_i for them, FP64 CGNE iteration counts (host check every iteration,
+    tol 1e-10) for the concave, increasing and decreasing orders at alpha = 1, and the
+    alpha sweep with the concave order; beside it the constant b = c = 1 of the table's
+    other rows at the same m and Ls.  Iteration counts on synthetic fields: parity
+    unpinned (the paper's are for MILC fields)."""
+    from paper_1501_04950_amd import synth
+    dims = w["dims"]
+    eta = torch.from_numpy(synth.z2_source(dims, w["seed"] + 100)).to(Ud.device)
+    probe = dwa.Context(dims, Ls, w["M5"], m, 1.0, 1.0, 1.0)
+    probe.set_links(Ud)
+    t0 = time.perf_counter()
+    lo, hi = probe.wilson_bounds(steps)
+    t_bounds = time.perf_counter() - t0
+    probe.close()
+    log(f"Zolotarev: |gamma5 D_w| in [{lo:.5f}, {hi:.5f}] ({steps} Lanczos steps, {t_bounds:.2f} s)")
+    out = {"workload": f"{dims[0]}^3x{dims[3]} Ls={Ls} m={m} M5={w['M5']} Z2 source, FP64 CGNE to 1e-10",
+           "lanczos_steps": steps, "lambda_min": lo, "lambda_max": hi, "bounds_s": round(t_bounds, 3)}
+    kw = dict(tol=1e-10, inner_prec="f64", check_every=1)
+    alphas = [0.15, 0.2, 0.25, 0.3, 0.4, 0.5, 0.6, 0.8, 1.0, 1.2]
+
+    def sweep(ctx):
+        ys, sts, rc = ctx.alpha_sweep(eta, alphas, **kw)
+        it = [s_["iters"] for s_ in sts]
+        n1 = it[alphas.index(1.0)]
+        best = min(range(len(alphas)), key=lambda i: it[i])
+        return ys[alphas.index(1.0)], {
+            "alpha": alphas, "iters": it, "rel_iters": [round(i / n1, 4) for i in it],
+            "best_alpha": alphas[best], "best_iters": it[best], "best_rel_iters": round(it[best] / n1, 4),
+            "speedup_1_minus_ratio": round(1 - it[best] / n1, 4), "status": rc}
+
+    y_ref = None
+    for order in ("concave", "increasing", "decreasing"):
+        om, delta = dwa.zolotarev(lo, hi, Ls, order)
+        ctx = dwa.Context(dims, Ls, w["M5"], m, 1.0, om, om)
+        ctx.set_links(Ud)
+        y1, rec = sweep(ctx)
+        ctx.close()
+        if order == "concave":
+            out["omega_concave"] = [round(v, 6) for v in om]
+            out["delta"] = delta
+            y_ref = y1
+        else:
+            rec["y1_rel_diff_vs_concave"] = float(torch.linalg.vector_norm(y1 - y_ref) /
+                                                  torch.linalg.vector_norm(y_ref))
+        out[order] = rec
+        log(f"  {order}: iters {rec['iters']}; best alpha {rec['best_alpha']}")
+    ctx = dwa.Context(dims, Ls, w["M5"], m, 1.0, 1.0, 1.0)
+    ctx.set_links(Ud)
+    _, out["constant_b1_c1"] = sweep(ctx)
+    ctx.close()
+    log(f"  constant b = c = 1: iters {out['constant_b1_c1']['iters']}")
+    return out
 
 
 def small_solves(torch, dwa, synth, dev):

@@ -281,6 +281,29 @@ int dwa_propagator_adjoint(dwa_ctx *ctx, void *gU, void *geta, double *galpha, d
                            const void *eta_prime, const dwa_solve_opts *opts,
                            dwa_solve_stats *stats);
 
+/* Zolotarev coefficients (Sec. 3: the Zolotarev row of the table and the paragraph on
+ * their ordering; App. A, eq.(polar)).  Host only, no device needed.
+ * With b_i = c_i = omega_i the kernel of eq.(argument) is omega_i H, H = gamma_5 D_w, and
+ * eq.(polar) approximates sign(H) by (1 - r(H)) / (1 + r(H)), r(x) = prod (1 - omega_i x) /
+ * (1 + omega_i x).  Returned are the omega_i minimising max |r| on [lmin, lmax], the
+ * spectrum of |H| (Zolotarev's third problem: 1/omega_j = lmax dn((2j - 1) K / (2 Ls), k'),
+ * k'^2 = 1 - (lmin/lmax)^2), in the order ordering = 0 increasing in i_5, 1 concave (the
+ * paper's choice: smallest at i_5 = 1 and Ls, largest in the centre), 2 decreasing.
+ * omega (host, Ls doubles) receives them; delta (host, may be NULL) max |r| on the
+ * interval, so |1 - sign approximation| <= 2 delta / (1 - delta) there.  DWA_EINVAL
+ * unless 0 < lmin < lmax is finite and 1 <= Ls <= 32. */
+int dwa_zolotarev(double lmin, double lmax, int Ls, int ordering, double *omega, double *delta);
+
+/* Spectral bounds of the Wilson kernel |H|, H = gamma_5 D_w (eq.(wilson), the context's
+ * links, M5 and boundary condition), for dwa_zolotarev: `steps` Lanczos steps on
+ * H^2 = D_w^dag D_w from a seeded start vector, on the GPU, and the extreme eigenvalues of
+ * the Lanczos tridiagonal matrix (Sturm bisection on the host).  lmin and lmax (host, either
+ * may be NULL) receive their square roots.  Ritz values lie inside the spectrum: lmax is a
+ * lower bound of the largest singular value of D_w and lmin an upper bound of the smallest;
+ * both converge as steps grows (exact once steps reaches the dimension 12 V).  Uses the
+ * context's workspace (no allocation).  DWA_EINVAL for steps outside [2, 100000]. */
+int dwa_wilson_bounds(dwa_ctx *ctx, int steps, double *lmin, double *lmax);
+
 /* Batches of right-hand sides (the paper's solves are 12 spin-colour sources per gauge
  * field, Sec. 3).  dwa_reserve_batch allocates the workspace for up to nmax fields of
  * this context (17 FP64 and 17 low-precision half fields per entry) and a

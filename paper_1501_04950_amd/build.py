@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 SOURCES = ([f"csrc/kernels_hop_{p}_{ns}.hip" for p in ("f64", "f32", "bf16") for ns in (8, 16, 32)]
            + ["csrc/kernels_f64.hip", "csrc/kernels_f32.hip", "csrc/kernels_bf16.hip",
               "csrc/kernels.hip", "csrc/adjoint.hip", "csrc/scratch.hip", "csrc/api.cpp",
-              "csrc/smat.cpp"])
+              "csrc/smat.cpp", "csrc/zolotarev.cpp"])
 LIB = os.path.join(PKG, "libdwa.so")
 OBJDIR = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

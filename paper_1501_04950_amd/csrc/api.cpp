@@ -119,9 +119,9 @@ int read_scalars(dwa_ctx* ctx) {
 }
 
 // |v|^2 of a field into a host double (synchronising)
-int host_norm2(dwa_ctx* ctx, int prec, const void* v, double* out) {
+int host_norm2(dwa_ctx* ctx, int prec, const void* v, double* out, size_t n = 0) {
   int nb = 0;
-  DWA_TRY(launch_norm2(ctx, prec, v, field_elems(ctx), bank(ctx, 3), &nb));
+  DWA_TRY(launch_norm2(ctx, prec, v, n ? n : field_elems(ctx), bank(ctx, 3), &nb));
   DWA_TRY(launch_sum_partials(ctx, bank(ctx, 3), nb, ctx->d_red));
   DWA_HIP(hipMemcpyAsync(out, ctx->d_red, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
           "norm readback");
@@ -2080,6 +2080,114 @@ int dwa_cgne_solve_batch(dwa_ctx* const* ctxs, int nctx, int nrhs, void* const* 
   for (int i = 0; i < nctx; ++i) ctxs[i]->stream = saved[i];
   if (status == DWA_ENOCONV) set_error("some field of the batch did not converge");
   return status;
+}
+
+// Extreme eigenvalues of a symmetric tridiagonal matrix (diagonal a[0..n), off-diagonal
+// b[1..n)) by bisection on the Sturm count: the number of eigenvalues below x is the number
+// of negative pivots of T - x.
+static int sturm_below(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0) ++cnt;
+  for (size_t i = 1; i < a.size(); ++i) {
+    const double qq = (q == 0.0) ? 1e-300 : q;
+    q = a[i] - x - b[i] * b[i] / qq;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+static double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, bool largest) {
+  double lo = a[0], hi = a[0];
+  for (size_t i = 0; i < a.size(); ++i) {  // Gershgorin interval
+    const double r = (i > 0 ? std::fabs(b[i]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i + 1]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  const int target = largest ? int(a.size()) - 1 : 0;  // eigenvalue index (ascending)
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(a, b, mid) > target) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+int dwa_wilson_bounds(dwa_ctx* ctx, int steps, double* lmin, double* lmax) {
+  DWA_TRY(check_ctx(ctx));
+  if (steps < 2 || steps > 100000) return einval("steps must be in [2, 100000]");
+  if (!lmin && !lmax) return einval("null outputs");
+  const size_t vh = ctx->Vh, half = 12 * vh;  // one parity of a 4D field
+  // 4D fields as [parity][12][Vh]: slices 0 and 1 of a workspace field (Ls >= 2)
+  double2* v = static_cast<double2*>(ctx->w64[W_R]);
+  double2* vp = static_cast<double2*>(ctx->w64[W_P]);
+  double2* w = static_cast<double2*>(ctx->w64[W_Z]);
+  double2* t = static_cast<double2*>(ctx->w64[W_Q]);
+  const size_t n = 2 * half;
+  // H_W = gamma_5 D_w (eq.(wilson)); out = H_W in, both parities: out_p = (4 + M5) in_p
+  // - 1/2 H in_{1-p}, then gamma_5 (spins 2, 3 = components 6..11 of each parity)
+  auto apply_hw = [&](double2* out, const double2* in) -> int {
+    const HopOp hb{in + half, out, in, nullptr, -0.5, 4.0 + ctx->M5, 0.0, MIX_IDENTITY, 0, 1, nullptr};
+    const HopOp hr{in, out + half, in + half, nullptr, -0.5, 4.0 + ctx->M5, 0.0, MIX_IDENTITY, 1, 1, nullptr};
+    DWA_TRY(launch_hop(ctx, DWA_F64, hb, nullptr));
+    DWA_TRY(launch_hop(ctx, DWA_F64, hr, nullptr));
+    for (int par = 0; par < 2; ++par) {
+      double2* lower = out + par * half + 6 * vh;
+      DWA_TRY(launch_axpby(ctx, DWA_F64, lower, -1.0, lower, 0.0, 6 * vh));
+    }
+    return DWA_OK;
+  };
+  // Re <a, b> over both parities
+  auto host_dot = [&](const double2* a, const double2* b, double* out) -> int {
+    const void* aa[2] = {a, a + half};
+    const void* bb[2] = {b, b + half};
+    return host_slice_dots(ctx, aa, bb, 1, false, out);
+  };
+  // seeded Gaussian start vector
+  {
+    std::vector<double2> h(n);
+    unsigned long long st = 0x9E3779B97F4A7C15ULL;
+    auto unif = [&]() {  // xorshift64*, then a double in (0, 1)
+      st ^= st >> 12;
+      st ^= st << 25;
+      st ^= st >> 27;
+      return ((st * 2685821657736338717ULL) >> 11) * (1.0 / 9007199254740992.0) + 0.5 / 9007199254740992.0;
+    };
+    for (auto& z : h) {
+      const double r = std::sqrt(-2.0 * std::log(unif())), ph = 2.0 * M_PI * unif();
+      z = make_double2(r * std::cos(ph), r * std::sin(ph));
+    }
+    DWA_HIP(hipMemcpyAsync(v, h.data(), sizeof(double2) * n, hipMemcpyHostToDevice, ctx->stream), "start vector");
+    DWA_HIP(hipStreamSynchronize(ctx->stream), "start vector sync");
+  }
+  double nv = 0.0;
+  DWA_TRY(host_norm2(ctx, DWA_F64, v, &nv, n));
+  DWA_TRY(launch_axpby(ctx, DWA_F64, v, 1.0 / std::sqrt(nv), v, 0.0, n));
+  DWA_TRY(launch_zero(ctx, DWA_F64, vp, n));
+  std::vector<double> al, be(1, 0.0);
+  for (int j = 0; j < steps; ++j) {
+    // w = H_W^2 v
+    DWA_TRY(apply_hw(t, v));
+    DWA_TRY(apply_hw(w, t));
+    double a = 0.0;
+    DWA_TRY(host_dot(v, w, &a));
+    al.push_back(a);
+    DWA_TRY(launch_axpby(ctx, DWA_F64, w, -a, v, 1.0, n));
+    if (j > 0) DWA_TRY(launch_axpby(ctx, DWA_F64, w, -be.back(), vp, 1.0, n));
+    double b2 = 0.0;
+    DWA_TRY(host_norm2(ctx, DWA_F64, w, &b2, n));
+    const double bn = std::sqrt(b2);
+    if (!(bn > 1e-14 * std::fabs(a)) || j + 1 == steps) break;  // Krylov space exhausted
+    be.push_back(bn);
+    DWA_TRY(launch_axpby(ctx, DWA_F64, w, 1.0 / bn, w, 0.0, n));
+    std::swap(vp, v);  // v_prev <- v
+    std::swap(v, w);   // v <- w / |w|; the old v_prev becomes the next w
+  }
+  be.resize(al.size());
+  const double emin = tridiag_eig(al, be, false), emax = tridiag_eig(al, be, true);
+  if (lmin) *lmin = std::sqrt(std::max(emin, 0.0));
+  if (lmax) *lmax = std::sqrt(std::max(emax, 0.0));
+  return DWA_OK;
 }
 
 // Host-only access to the site-local matrices (no device needed); used to check

@@ -123,6 +123,9 @@ def lib():
         "dwa_cgne_solve_batch": (c_int, [POINTER(c_void_p), c_int, c_int, POINTER(c_void_p),
                                          POINTER(c_void_p), POINTER(dwa_solve_opts),
                                          POINTER(dwa_solve_stats)]),
+        "dwa_zolotarev": (c_int, [c_double, c_double, c_int, c_int, POINTER(c_double),
+                                  POINTER(c_double)]),
+        "dwa_wilson_bounds": (c_int, [P, c_int, POINTER(c_double), POINTER(c_double)]),
         "dwa_autotune": (c_int, [P, c_int, c_int, POINTER(dwa_tune_entry), c_int, POINTER(c_int)]),
         "dwa_set_tuning": (c_int, [P, c_int, c_int, c_int, c_int, c_int]),
         "dwa_get_tuning": (c_int, [P, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int),
@@ -176,6 +179,21 @@ def dwa_debug_smatrix(dims, Ls, M5, m, alpha, b, c, kind):
     k = MIX_KINDS[kind] if isinstance(kind, str) else int(kind)
     check(lib().dwa_debug_smatrix(byref(p), k, out.ctypes.data_as(POINTER(c_double))))
     return out
+
+
+ZOLO_ORDERS = {"increasing": 0, "concave": 1, "decreasing": 2}
+
+
+def zolotarev(lmin, lmax, Ls, ordering="concave"):
+    """Zolotarev coefficients omega_i (per slice i_5) for b_i = c_i = omega_i and the
+    deviation delta = max |prod (1 - omega x)/(1 + omega x)| on [lmin, lmax]
+    (dwa_zolotarev; host only)."""
+    om = np.zeros(int(Ls))
+    d = c_double(0.0)
+    o = ZOLO_ORDERS[ordering] if isinstance(ordering, str) else int(ordering)
+    check(lib().dwa_zolotarev(float(lmin), float(lmax), int(Ls), o,
+                              om.ctypes.data_as(POINTER(c_double)), byref(d)))
+    return om, d.value
 
 
 def _torch():
@@ -439,6 +457,13 @@ class Context:
         if gc is not None:
             out["c"] = gc
         return out
+
+    def wilson_bounds(self, steps=200):
+        """(lambda_min, lambda_max) estimates of |gamma_5 D_w| by Lanczos on the GPU
+        (dwa_wilson_bounds)."""
+        lo, hi = c_double(0.0), c_double(0.0)
+        check(lib().dwa_wilson_bounds(self._h, int(steps), byref(lo), byref(hi)))
+        return lo.value, hi.value
 
     def reserve_batch(self, nmax):
         check(lib().dwa_reserve_batch(self._h, int(nmax)))
