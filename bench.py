@@ -54,6 +54,10 @@ def parse():
                     help="skip the batched 3-lattice x 12-source solve")
     ap.add_argument("--no-zolo", action="store_true",
                     help="skip the Zolotarev-coefficient study")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the eq.(redblack) vs eq.(redblack1) comparison")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="skip the overlap-operator application")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 4^4 and 8^3x16 time-to-solution runs")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -284,6 +288,16 @@ def main():
     if not args.no_zolo:
         zolo = zolotarev_study(torch, dwa, Ud, w, args)
 
+    # --- the Schur forms of Sec. 3: eq.(redblack) against eq.(redblack1) -------------
+    forms = None
+    if not args.no_forms:
+        forms = schur_form_study(torch, dwa, Ud, w, zolo)
+
+    # --- the overlap operator through the 5D engine ---------------------------------
+    ovl = None
+    if not args.no_overlap:
+        ovl = overlap_study(torch, dwa, Ud, w, eta_d, y if y is not None else None)
+
     # --- the small workloads (launch-latency bound): time to solution ----------------
     small = None
     if not args.no_small:
@@ -329,6 +343,8 @@ def main():
         "tuning": tuning,
         "small_workloads": small,
         "zolotarev": zolo,
+        "schur_forms": forms,
+        "overlap": ovl,
         "gradients": grad,
         "alpha_sweep": sweep,
         "batch": batch,
@@ -665,6 +681,63 @@ def zolotarev_study(torch, dwa, Ud, w, args, Ls=10, m=0.06, steps=300):
     ctx.close()
     log(f"  constant b = c = 1: iters {out['constant_b1_c1']['iters']}")
     return out
+
+
+def schur_form_study(torch, dwa, Ud, w, zolo):
+    """Sec. 3's comparison of the Schur forms on the paper-shaped field: CGNE iteration
+    counts (FP64, tol 1e-10 on each form's own residual, alpha = 1) of eq.(redblack),
+    eq.(redblack1) and eq.(redblack1) with its rows scaled, for the bench's Moebius
+    coefficients (b = 1.5, c = 0.5, Ls = 16, m = 0.01) and, when the Zolotarev study ran,
+    its concave Zolotarev coefficients (Ls = 10, m = 0.06).  Every form reaches the same
+    solution; the eq.(redblack) residual of each result is reported.  Counts on synthetic
+    fields: parity unpinned."""
+    from paper_1501_04950_amd import synth
+    dims = w["dims"]
+    eta = torch.from_numpy(synth.z2_source(dims, w["seed"] + 100)).to(Ud.device)
+    cases = [("moebius b=1.5 c=0.5", w["Ls"], w["m"], w["b"], w["c"])]
+    if zolo:
+        om = np.array(zolo["omega_concave"])
+        cases.append(("zolotarev concave", len(om), 0.06, om, om))
+    out = {}
+    for name, Ls, m, b, c in cases:
+        ctx = dwa.Context(dims, Ls, w["M5"], m, 1.0, b, c)
+        ctx.set_links(Ud)
+        rec, y0 = {"Ls": Ls, "m": m}, None
+        for form in ("redblack", "redblack1", "redblack1_scaled"):
+            y, st, rc = ctx.propagator_form(eta, form, tol=1e-10, maxiter=20000)
+            if y0 is None:
+                y0 = y
+            rec[form] = {"iters": st["iters"], "status": rc, "redblack_resid": st["rel_resid"],
+                         "time_s": round(st["time_ms"] / 1e3, 3),
+                         "y1_rel_diff_vs_redblack": float(torch.linalg.vector_norm(y - y0) /
+                                                          torch.linalg.vector_norm(y0))}
+            log(f"Schur form {form} ({name}): {st['iters']} iters, eq.(redblack) resid {st['rel_resid']:.1e}")
+        out[name] = rec
+        ctx.close()
+    return out
+
+
+def overlap_study(torch, dwa, Ud, w, eta, y_mixed):
+    """The 4D overlap operator D_OV(m) through one 5D solve of mass 1 (App. A,
+    eq.(startprop)) on the paper-shaped field: the time of one application (FP64 CGNE to
+    1e-10) and the residual |D_OV(m) y_1 - eta| / |eta| of the bench's mixed-precision y_1."""
+    dims = w["dims"]
+    ctx = dwa.Context(dims, w["Ls"], w["M5"], 1.0, 1.0, w["b"], w["c"])
+    ctx.set_links(Ud)
+    ctx.overlap_apply(eta, w["m"], tol=1e-10, check_every=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, st, rc = ctx.overlap_apply(eta, w["m"], tol=1e-10, check_every=5)
+    torch.cuda.synchronize()
+    rec = {"workload": f"D_OV(m={w['m']}) on the Z2 source, mass-1 solve in FP64 to 1e-10",
+           "time_s": round(time.perf_counter() - t0, 4), "iters": st["iters"], "status": rc}
+    if y_mixed is not None:
+        back, st2, rc2 = ctx.overlap_apply(y_mixed, w["m"], tol=1e-12, check_every=5)
+        rec["residual_of_mixed_y1"] = float(torch.linalg.vector_norm(back - eta) / torch.linalg.vector_norm(eta))
+    log(f"overlap apply: {rec['time_s']} s, {st['iters']} iters; D_OV y_1 residual "
+        f"{rec.get('residual_of_mixed_y1')}")
+    ctx.close()
+    return rec
 
 
 def small_solves(torch, dwa, synth, dev):

@@ -243,6 +243,33 @@ int dwa_cgne_solve(dwa_ctx *ctx, void *x_b, const void *rhs_b, const dwa_solve_o
 int dwa_propagator(dwa_ctx *ctx, void *y1, const void *eta, const dwa_solve_opts *opts,
                    dwa_solve_stats *stats, void *psi5);
 
+/* The propagator of dwa_propagator with the Schur system in one of the forms of Sec. 3,
+ * for comparing their CGNE iteration counts (FP64 CGLS, every scalar read on the host, so
+ * all forms run the same algorithm; opts->tol and opts->maxiter are used):
+ *   form 0: eq.(redblack),  D_bb = 1 - I_bb^-1 D_br I_rr^-1 D_rb;
+ *   form 1: eq.(redblack1), I_bb - D_br I_rr^-1 D_rb = I_bb D_bb, right-hand side I_bb phi';
+ *   form 2: eq.(redblack1) with every row s whose coefficient max(b_s, c_s) exceeds one
+ *           divided by it (the row scaling the paper describes after eq.(redblack1)).
+ * Each solve stops on its own relative residual <= tol; stats->rel_resid is the residual of
+ * eq.(redblack), |phi' - D_bb psi_b| / |phi'|, of the result, so the forms compare at equal
+ * accuracy.  All forms have the same solution, hence the same y_1.  DWA_EINVAL for another
+ * form. */
+int dwa_propagator_form(dwa_ctx *ctx, int form, void *y1, const void *eta, const dwa_solve_opts *opts,
+                        dwa_solve_stats *stats);
+
+/* The 4D overlap operator through the 5D engine (App. A: D^5_OV(m) =
+ * R^-1 D_DW(1)^-1 D_DW(m) R, eq.(startprop); its (1,1) block is
+ * D_OV(m) = 1/2 [(1 + m) + (1 - m) gamma_5 (S - 1)/(S + 1)] with S the product of the transfer
+ * matrices of the context's b_i, c_i): out = D_OV(m) in = [P^-1 D_1(1)^-1 D_1(m) P (in, 0, ..,
+ * 0)]_1.  One 5D solve: rho = D_1(m) P (in, 0, ..., 0) on the wall slices, D_alpha(1) psi =
+ * rho by the red-black CGNE of dwa_cgne_solve with opts (the context's alpha, mass 1:
+ * well conditioned), out = P- psi_1 + P+ psi_Ls.  The context must have mass 1 (DWA_EINVAL
+ * otherwise); m is the overlap mass.  out and in are canonical complex128 [V][4][3] on the
+ * device and must not overlap.  Its inverse for mass m is dwa_propagator on a context of
+ * mass m.  Returns like dwa_propagator. */
+int dwa_overlap_apply(dwa_ctx *ctx, double m, void *out, const void *in, const dwa_solve_opts *opts,
+                      dwa_solve_stats *stats);
+
 /* Change alpha of an existing context (eq.(mobius1): alpha multiplies the P+/P- terms
  * of every row; the 4D propagator does not depend on it, Sec. 2 / eq.(tosolve1)).
  * Rebuilds the site-local matrices for the new alpha after the context's stream has
@@ -367,7 +394,9 @@ const char *dwa_last_error(void);
 /* Host-only (no device needed): the real Ls x Ls fifth-dimension matrices the
  * kernels apply, per chirality, out = [2][Ls][Ls] (index 0 = P+, 1 = P-).  kind:
  * 0 identity, 1 B G, 2 N = B I_1^-1, 3 G^-1 I_1^-1, 4 g5 I_1^-T G^-1, 5 N^T,
- * 6 G B^T g5, 7 I_1^-1, 8 I_1 G (the site-local block I of D_alpha, eq.(redblack)).
+ * 6 G B^T g5, 7 I_1^-1, 8 I_1 G (the site-local block I of D_alpha, eq.(redblack)),
+ * 9 (I_1 G)^T, 10 W I_1 G, 11 (W I_1 G)^T with W = diag(1 / max(1, b_s, c_s)) (the row
+ * scaling of eq.(redblack1)).
  * Here D_1 = D_w B + C slice by slice, I_1 = (4 + M5) B + C and D_alpha = D_1 G
  * with G = diag(P- + alpha P+, alpha, ..., alpha, P+ + alpha P-) (Sec. 2). */
 int dwa_debug_smatrix(const dwa_params *p, int kind, double *out);

@@ -13,20 +13,28 @@ from concurrent.futures import ProcessPoolExecutor
 from . import redblack
 
 
+def _solve(U, eta, p, tol, form):
+    if form is None:
+        return redblack.propagator(U, eta, p, tol=tol)
+    return redblack.propagator_form(U, eta, p, form, tol=tol)
+
+
 def _one(args):
-    U, eta, p, tol = args
+    U, eta, p, tol, form = args
     try:  # one BLAS thread per worker: the workers already fill the cores
         from threadpoolctl import threadpool_limits
         with threadpool_limits(1):
-            y, info = redblack.propagator(U, eta, p, tol=tol)
+            y, info = _solve(U, eta, p, tol, form)
     except ImportError:
-        y, info = redblack.propagator(U, eta, p, tol=tol)
+        y, info = _solve(U, eta, p, tol, form)
     return y, info.iters
 
 
-def propagators(U, etas, p, tol=1e-10, workers=None):
-    """[(y_1, CGLS iterations)] of redblack.propagator for each source in etas."""
-    jobs = [(U, e, p, tol) for e in etas]
+def propagators(U, etas, p, tol=1e-10, workers=None, forms=None):
+    """[(y_1, CGLS iterations)] of redblack.propagator for each source in etas, or of
+    redblack.propagator_form with forms[i] for source i."""
+    forms = [None] * len(etas) if forms is None else list(forms)
+    jobs = [(U, e, p, tol, f) for e, f in zip(etas, forms)]
     if workers is None:
         workers = min(len(jobs), len(os.sched_getaffinity(0)), 16)
     if workers <= 1:

@@ -140,6 +140,43 @@ class RedBlack:
         t = self.I_inv_dag_apply(t)
         return self.black * (yb - self.hop_dag(t))
 
+    # --- eq.(redblack1) and its row-scaled form (Sec. 3) --------------------
+    def I_dag_apply(self, psi5):
+        return self._site_apply(np.conj(self.I_mat.T), psi5)
+
+    def Dbb1(self, xb):
+        """D'_bb x = I_bb x - D_br I_rr^-1 D_rb x (eq.(redblack1))."""
+        return self.black * self.I(self.black * xb) - self.D_br(self.I_inv_apply(self.D_rb(xb)))
+
+    def Dbb1_dag(self, yb):
+        """D'_bb^dag y = I_bb^dag y - D_rb^dag I_rr^-dag D_br^dag y."""
+        t = self.red * self.hop_dag(self.black * yb)
+        t = self.I_inv_dag_apply(t)
+        return self.black * (self.I_dag_apply(self.black * yb) - self.hop_dag(t))
+
+    def row_weights(self):
+        """The row scaling described after eq.(redblack1): row s (the output slice, the row
+        that holds the coefficients b_s, c_s) is divided by its coefficient when that
+        exceeds one.  Reading: the coefficient of row s is max(b_s, c_s) (b_s = c_s =
+        omega_s for Zolotarev coefficients)."""
+        p = self.p
+        return 1.0 / np.maximum(1.0, np.maximum(np.abs(p.b), np.abs(p.c)))
+
+    def scale_rows(self, psi5):
+        return self.row_weights()[:, None, None, None] * psi5
+
+    def schur_form(self, form):
+        """(apply A, apply A^dag, rhs map) of the Schur system of form 0 (eq.(redblack)),
+        1 (eq.(redblack1)) or 2 (eq.(redblack1) with scaled rows); every form has the
+        solution of D_bb x = phi'."""
+        if form == 0:
+            return self.Dbb, self.Dbb_dag, lambda phi: phi
+        if form == 1:
+            return self.Dbb1, self.Dbb1_dag, lambda phi: self.black * self.I(phi)
+        w = self.scale_rows
+        return (lambda x: w(self.Dbb1(x)), lambda y: self.Dbb1_dag(w(y)),
+                lambda phi: w(self.black * self.I(phi)))
+
     def schur_rhs(self, rho):
         """phi' = I_bb^-1 (rho_b - D_br I_rr^-1 rho_r)."""
         t = self.I_inv_apply(self.red * rho)
@@ -223,6 +260,18 @@ def propagator(U, eta, p: Params, tol=1e-10, maxiter=100000, return_psi=False):
     if return_psi:
         return y1, info, psi
     return y1, info
+
+
+def propagator_form(U, eta, p: Params, form, tol=1e-10, maxiter=100000):
+    """y_1 with the Schur system in form 0, 1 or 2 (see RedBlack.schur_form), CGLS stopping
+    on that form's own residual."""
+    rb = RedBlack(U, p)
+    rho = source_rhs(U, eta, p)
+    phi = rb.schur_rhs(rho)
+    A, Ad, to_rhs = rb.schur_form(form)
+    psi_b, info = cgls(A, Ad, to_rhs(phi), tol, maxiter)
+    psi = psi_b + rb.reconstruct_red(psi_b, rho)
+    return extract_y1(psi), info
 
 
 def solve_unpreconditioned(U, rho, p: Params, tol=1e-12, maxiter=100000):

@@ -1623,8 +1623,77 @@ int dwa_cgne_solve(dwa_ctx* ctx, void* x, const void* rhs, const dwa_solve_opts*
   return status;
 }
 
-int dwa_propagator(dwa_ctx* ctx, void* y1, const void* eta, const dwa_solve_opts* o,
-                   dwa_solve_stats* stats, void* psi5) {
+// CGLS on one of the Schur forms of Sec. 3 for D_bb x = rhs (FP64, plain: every scalar goes
+// through the host, so the three forms run the same algorithm):
+//   form 0: eq.(redblack),  A = D_bb = 1 - I_bb^-1 D_br I_rr^-1 D_rb,  b = rhs;
+//   form 1: eq.(redblack1), A = I_bb D_bb = I_bb - D_br I_rr^-1 D_rb,  b = I_bb rhs;
+//   form 2: eq.(redblack1) with its rows scaled, A = W I_bb D_bb, b = W I_bb rhs, W dividing
+//           every row s whose coefficient max(b_s, c_s) exceeds one by that coefficient.
+// All three have the solution x of D_bb x = rhs.  Stops when |b - A x| <= tol |b| (the
+// form's own residual); *rel receives |rhs - D_bb x| / |rhs| of the result.
+// Workspace: W_R, W_P, W_Z, W_Q, W_W, W_U, W_RES, W_OPB, W_OPR.
+static int cgls_form(dwa_ctx* ctx, int form, void* x, const void* rhs, double tol, int maxiter,
+                     CgResult* res, double* rel) {
+  void** W = ctx->w64;
+  const size_t n = field_elems(ctx);
+  void *r = W[W_R], *p = W[W_P], *z = W[W_Z], *q = W[W_Q], *tmp = W[W_W], *b = W[W_RES];
+  const int mixA = form == 2 ? MIX_W_I : MIX_I_ALPHA, mixAT = form == 2 ? MIX_W_I_T : MIX_I_ALPHA_T;
+  auto applyA = [&](void* out, const void* in) -> int {
+    if (form == 0) return apply_dbb(ctx, DWA_F64, out, in, W[W_OPB], W[W_OPR]);
+    DWA_TRY(apply_dbb(ctx, DWA_F64, tmp, in, W[W_OPB], W[W_OPR]));
+    return launch_smix(ctx, DWA_F64, mixA, out, tmp, nullptr, 0.0, ctx->Ls, nullptr, nullptr);
+  };
+  auto applyAd = [&](void* out, const void* in) -> int {
+    if (form == 0) return apply_dbbdag(ctx, DWA_F64, out, in, W[W_OPB], W[W_OPR]);
+    DWA_TRY(launch_smix(ctx, DWA_F64, mixAT, tmp, in, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+    return apply_dbbdag(ctx, DWA_F64, out, tmp, W[W_OPB], W[W_OPR]);
+  };
+  if (form == 0) DWA_TRY(launch_axpby(ctx, DWA_F64, b, 1.0, rhs, 0.0, n));
+  else DWA_TRY(launch_smix(ctx, DWA_F64, mixA, b, rhs, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
+  double b2 = 0.0, r2 = 0.0, gamma = 0.0, q2 = 0.0;
+  DWA_TRY(host_norm2(ctx, DWA_F64, b, &b2));
+  DWA_TRY(launch_zero(ctx, DWA_F64, x, n));
+  DWA_TRY(launch_axpby(ctx, DWA_F64, r, 1.0, b, 0.0, n));
+  DWA_TRY(applyAd(z, r));
+  DWA_TRY(host_norm2(ctx, DWA_F64, z, &gamma));
+  DWA_TRY(launch_axpby(ctx, DWA_F64, p, 1.0, z, 0.0, n));
+  res->n_dbb += 1;
+  r2 = b2;
+  int k = 0;
+  while (b2 > 0.0 && r2 > tol * tol * b2 && k < maxiter) {
+    DWA_TRY(applyA(q, p));
+    DWA_TRY(host_norm2(ctx, DWA_F64, q, &q2));
+    if (!(q2 > 0.0) || !std::isfinite(q2)) {
+      res->breakdown = 1;
+      break;
+    }
+    const double a = gamma / q2;
+    DWA_TRY(launch_axpby(ctx, DWA_F64, x, a, p, 1.0, n));
+    DWA_TRY(launch_axpby(ctx, DWA_F64, r, -a, q, 1.0, n));
+    DWA_TRY(host_norm2(ctx, DWA_F64, r, &r2));
+    DWA_TRY(applyAd(z, r));
+    double g2 = 0.0;
+    DWA_TRY(host_norm2(ctx, DWA_F64, z, &g2));
+    DWA_TRY(launch_axpby(ctx, DWA_F64, p, 1.0, z, g2 / gamma, n));
+    gamma = g2;
+    res->n_dbb += 2;
+    ++k;
+  }
+  res->iters = k;
+  res->converged = b2 == 0.0 || r2 <= tol * tol * b2;
+  res->rel_recursive = b2 > 0.0 ? std::sqrt(r2 / b2) : 0.0;
+  double rh2 = 0.0;
+  DWA_TRY(host_norm2(ctx, DWA_F64, rhs, &rh2));
+  return true_residual64(ctx, x, rhs, std::sqrt(rh2), rel, nullptr);
+}
+
+// y = [P^-1 D_1(m)^-1 D_1(ms) P (eta, 0, ..., 0)]_1 = D_OV(m)^-1 D_OV(ms) eta (App. A and B,
+// eq.(startprop) and eq.(tosolve)), m the context's mass; solved through D_alpha(m) =
+// D_1(m) G, whose G drops out of the extraction.  ms = 1 is the propagator (D_OV(1) = 1).
+// form < 0: the Schur system is solved by dwa_cgne_solve (all options); form 0..2: by
+// cgls_form in FP64 (opts->tol and maxiter only).
+static int propagator_impl(dwa_ctx* ctx, double ms, void* y1, const void* eta, const dwa_solve_opts* o,
+                           dwa_solve_stats* stats, void* psi5, int form = -1) {
   DWA_TRY(check_ctx(ctx));
   if (!y1 || !eta || !o) return einval("null argument");
   void** W = ctx->w64;
@@ -1640,18 +1709,36 @@ int dwa_propagator(dwa_ctx* ctx, void* y1, const void* eta, const dwa_solve_opts
     return DWA_ENAN;
   }
   const int Ls = ctx->Ls;
-  // rho = D_1(1) P (eta, 0, ..., 0): wall slices only
-  DWA_TRY(launch_source(ctx, W[W_CHI_B], W[W_CHI_R], W[W_RHO_B], W[W_RHO_R], eta));
+  // rho = D_1(ms) P (eta, 0, ..., 0): wall slices only
+  DWA_TRY(launch_source(ctx, W[W_CHI_B], W[W_CHI_R], W[W_RHO_B], W[W_RHO_R], eta, ms));
   DWA_TRY(wall_hops(ctx, W[W_CHI_B], W[W_CHI_R], W[W_RHO_B], W[W_RHO_R]));
   // phi' = I_bb^-1 (rho_b - D_br I_rr^-1 rho_r) = G^-1 I^-1 (rho_b + 1/2 H_br N rho_r)
   DWA_TRY(launch_smix(ctx, DWA_F64, MIX_N, W[W_T], W[W_RHO_R], nullptr, 0.0, Ls, nullptr, nullptr));
   HopOp prep{W[W_T], W[W_PHI], W[W_RHO_B], nullptr, 0.5, 1.0, 0.0, MIX_GINV_IINV, 0, Ls, nullptr};
   DWA_TRY(launch_hop(ctx, DWA_F64, prep, nullptr));
   // D_bb psi_b = phi'
-  dwa_solve_opts so = *o;
-  so.warm_start = 0;
-  int status = dwa_cgne_solve(ctx, W[W_PSI_B], W[W_PHI], &so, stats);
-  if (status != DWA_OK && status != DWA_ENOCONV) return status;
+  int status = DWA_OK;
+  if (form < 0) {
+    dwa_solve_opts so = *o;
+    so.warm_start = 0;
+    status = dwa_cgne_solve(ctx, W[W_PSI_B], W[W_PHI], &so, stats);
+    if (status != DWA_OK && status != DWA_ENOCONV) return status;
+  } else {
+    const auto t0 = std::chrono::steady_clock::now();
+    CgResult cr;
+    double rel = 0.0;
+    DWA_TRY(cgls_form(ctx, form, W[W_PSI_B], W[W_PHI], o->tol, o->maxiter, &cr, &rel));
+    status = cr.breakdown ? DWA_EBREAKDOWN : (cr.converged ? DWA_OK : DWA_ENOCONV);
+    if (stats) {
+      *stats = dwa_solve_stats{};
+      stats->iters = cr.iters;
+      stats->converged = cr.converged;
+      stats->rel_resid = rel;
+      stats->n_Dbb = cr.n_dbb + 1;
+      stats->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status == DWA_EBREAKDOWN) return status;
+  }
   // psi_r = I_rr^-1 (rho_r - D_rb psi_b) = G^-1 I^-1 (rho_r + 1/2 H_rb B G psi_b)
   DWA_TRY(launch_smix(ctx, DWA_F64, MIX_BG, W[W_OPB], W[W_PSI_B], nullptr, 0.0, Ls, nullptr, nullptr));
   HopOp rec{W[W_OPB], W[W_PSI_R], W[W_RHO_R], nullptr, 0.5, 1.0, 0.0, MIX_GINV_IINV, 1, Ls, nullptr};
@@ -1663,6 +1750,29 @@ int dwa_propagator(dwa_ctx* ctx, void* y1, const void* eta, const dwa_solve_opts
   }
   DWA_HIP(hipStreamSynchronize(ctx->stream), "propagator sync");
   return status;
+}
+
+int dwa_propagator(dwa_ctx* ctx, void* y1, const void* eta, const dwa_solve_opts* o,
+                   dwa_solve_stats* stats, void* psi5) {
+  return propagator_impl(ctx, 1.0, y1, eta, o, stats, psi5);
+}
+
+int dwa_propagator_form(dwa_ctx* ctx, int form, void* y1, const void* eta, const dwa_solve_opts* o,
+                        dwa_solve_stats* stats) {
+  if (form < 0 || form > 2) return einval("form must be 0, 1 or 2");
+  if (o && !(o->tol > 0.0)) return einval("bad tolerance");
+  if (o && o->maxiter < 0) return einval("bad maxiter");
+  return propagator_impl(ctx, 1.0, y1, eta, o, stats, nullptr, form);
+}
+
+int dwa_overlap_apply(dwa_ctx* ctx, double m, void* out, const void* in, const dwa_solve_opts* o,
+                      dwa_solve_stats* stats) {
+  DWA_TRY(check_ctx(ctx));
+  if (ctx->m != 1.0) return einval("dwa_overlap_apply needs a context of mass 1 (the D_1(1) solve)");
+  if (!std::isfinite(m)) return einval("mass must be finite");
+  if (!out || !in || !o) return einval("null argument");
+  if (out == in) return einval("out and in must not overlap");
+  return propagator_impl(ctx, m, out, in, o, stats, nullptr);
 }
 
 int dwa_alpha_sweep(dwa_ctx* ctx, const double* alphas, int n, void* y1, const void* eta,

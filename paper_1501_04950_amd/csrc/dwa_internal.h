@@ -151,7 +151,10 @@ enum MixKind {
   MIX_NT,          // N^T           : after the first hop of D_bb^dag
   MIX_G_BT_G5,     // G B^T g5      : after the second hop of D_bb^dag
   MIX_IINV,        // I^-1 (alpha = 1 part only, used by tests)
-  MIX_I_ALPHA,     // I_1 G         : the site-local block I of D_alpha (tests)
+  MIX_I_ALPHA,     // I_1 G         : the site-local block I of D_alpha (tests, eq.(redblack1))
+  MIX_I_ALPHA_T,   // (I_1 G)^T     : its adjoint, per chirality
+  MIX_W_I,         // W I_1 G       : I with the rows of large coefficients scaled down
+  MIX_W_I_T,       // (W I_1 G)^T
   MIX_COUNT
 };
 
@@ -354,7 +357,10 @@ int launch_fold_acc(dwa_ctx* ctx, int xprec, void* X, void* xl, size_t n, double
 // RES = PHI - Q in FP64 and per-block partial sums of |RES|^2 (nblocks per field)
 int launch_residual(dwa_ctx* ctx, void* res, const void* phi, const void* q, size_t n, double* partials,
                     int* nblocks, int nrhs = 1);
-int launch_source(dwa_ctx* ctx, void* chi_b, void* chi_r, void* aux_b, void* aux_r, const void* eta);
+// rho = D_1(ms) P (eta, 0, ..., 0) on the two wall slices: chi (the D_w part) and aux (the
+// site-local part); the propagator uses ms = 1 (eq.(tosolve1))
+int launch_source(dwa_ctx* ctx, void* chi_b, void* chi_r, void* aux_b, void* aux_r, const void* eta,
+                  double ms = 1.0);
 int launch_extract(dwa_ctx* ctx, void* y1, const void* psi_b, const void* psi_r);
 int launch_check_finite(dwa_ctx* ctx, const void* canon, size_t ncomplex, int* d_flag);
 

@@ -1191,9 +1191,11 @@ int launch_smix_p(dwa_ctx* ctx, int mix, void* out, const void* in, const void* 
     return DWA_EINVAL;
   }
   const int grid = (int)((6u * (unsigned)ctx->Vh + 255) / 256);
-  if (mix == MIX_I_ALPHA) {  // the site-local block I of D_alpha: dense table, FP64 only
+  if (mix == MIX_I_ALPHA || mix == MIX_I_ALPHA_T || mix == MIX_W_I || mix == MIX_W_I_T) {
+    // the site-local block I of D_alpha and its forms for eq.(redblack1): dense tables
+    // (the kernel's dense path reads the table of the kind given), FP64 only
     if constexpr (S::prec == DWA_F64) {
-      const MixTables T = mix_tables<S>(ctx, MIX_I_ALPHA);
+      const MixTables T = mix_tables<S>(ctx, mix);
       hipLaunchKernelGGL((smix_kernel<S, 0, MIX_I_ALPHA, true>), dim3(grid, nrhs), dim3(256), 0,
                          ctx->stream, (double2*)out, (const double2*)in, (const double2*)post,
                          post_coef, T, ctx->Ls, (unsigned)ctx->Vh, partials);

@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) source_kernel(double2* __restrict__ chi_b
                                                      const double2* __restrict__ eta,
                                                      const int* __restrict__ cb2lex, int Ls,
                                                      unsigned Vh, double M5, double b0, double c0,
-                                                     double bL, double cL) {
+                                                     double bL, double cL, double ms) {
   const size_t n = size_t(2) * Ls * 12 * Vh;
   for (size_t t = blockIdx.x * size_t(blockDim.x) + threadIdx.x; t < n;
        t += size_t(gridDim.x) * blockDim.x) {
@@ -76,18 +76,23 @@ __global__ void __launch_bounds__(256) source_kernel(double2* __restrict__ chi_b
     if (s == 0 || s == (unsigned)(Ls - 1)) {
       e = eta[size_t(cb2lex[par * Vh + cb]) * 12 + comp];
     }
-    double f = 0.0;
+    // rows 1 and Ls of eq.(mobius1) at alpha = 1 and mass ms on P (eta, 0, ..., 0):
+    //   rho_1  = (b_1 D_w + 1) P- eta - ms (c_1 D_w - 1) P+ eta,
+    //   rho_Ls = (b_Ls D_w + 1) P+ eta - ms (c_Ls D_w - 1) P- eta;
+    // chi is the part D_w acts on, the remainder is site-local
+    double f = 0.0, g = 0.0;
     if (s == 0) {
-      f = upper ? -c0 : b0;
+      f = upper ? -ms * c0 : b0;
+      g = upper ? ms : 1.0;
       wall = true;
     } else if (s == (unsigned)(Ls - 1)) {
-      f = upper ? bL : -cL;
+      f = upper ? bL : -ms * cL;
+      g = upper ? 1.0 : ms;
       wall = true;
     }
     const double2 cv = make_double2(f * e.x, f * e.y);
     chi[idx] = cv;
-    // rho_0 and rho_{Ls-1} each carry + eta
-    const double ne = wall ? 1.0 : 0.0;
+    const double ne = wall ? g : 0.0;
     aux[idx] = make_double2((4.0 + M5) * cv.x + ne * e.x, (4.0 + M5) * cv.y + ne * e.y);
   }
 }
@@ -373,13 +378,13 @@ int launch_sum_partials(dwa_ctx* ctx, const double* partials, int n, double* out
 }
 
 int launch_source(dwa_ctx* ctx, void* chi_b, void* chi_r, void* aux_b, void* aux_r,
-                  const void* eta) {
+                  const void* eta, double ms) {
   const int Ls = ctx->Ls;
   const size_t n = size_t(2) * Ls * 12 * ctx->Vh;
   hipLaunchKernelGGL(source_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream,
                      (double2*)chi_b, (double2*)chi_r, (double2*)aux_b, (double2*)aux_r,
                      (const double2*)eta, ctx->d_cb2lex, Ls, (unsigned)ctx->Vh, ctx->M5, ctx->b[0],
-                     ctx->c[0], ctx->b[Ls - 1], ctx->c[Ls - 1]);
+                     ctx->c[0], ctx->b[Ls - 1], ctx->c[Ls - 1], ms);
   return hip_fail(hipGetLastError(), "source launch");
 }
 

@@ -20,6 +20,7 @@
 //   D_bb^dag = 1 - 1/4 G B^T g5 H_br N^T H_rb g5 I_1^-T G^-1
 // (the adjoint uses H_rb^dag = g5 H_br g5 and that B, N, I_1, G are real and act
 // within one chirality).  This file builds every matrix these formulas need.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -265,6 +266,15 @@ bool build_smatrices(int Ls, double M5, double m, double alpha, const double* b,
     put(MIX_G_BT_G5, ch, GBTg5);
     put(MIX_IINV, ch, I1inv);
     put(MIX_I_ALPHA, ch, mul(I1, G[ch], n));
+    put(MIX_I_ALPHA_T, ch, transpose(mul(I1, G[ch], n), n));
+    // row scaling of eq.(redblack1) (Sec. 3): a row s whose coefficient exceeds one is
+    // divided by it; the coefficient of row s is max(b_s, c_s) (b_s = c_s = omega_s for
+    // Zolotarev coefficients)
+    Mat Wd = zeros(n);
+    for (int s = 0; s < n; ++s) Wd[s * n + s] = 1.0 / std::max(1.0, std::max(std::fabs(b[s]), std::fabs(c[s])));
+    const Mat WI = mul(Wd, mul(I1, G[ch], n), n);
+    put(MIX_W_I, ch, WI);
+    put(MIX_W_I_T, ch, transpose(WI, n));
 
     if (sweeps) {
       // P+ (ch 0): B and I_1 are lower cyclic bidiagonal; P- (ch 1): upper
@@ -286,6 +296,11 @@ bool build_smatrices(int Ls, double M5, double m, double alpha, const double* b,
       prog[MIX_G_BT_G5] = {bidiag_stage(BT, n, !low), scale_stage(sg)};
       prog[MIX_IINV] = {solve_stage(I1, n, low)};
       prog[MIX_I_ALPHA] = {scale_stage(g), bidiag_stage(I1, n, low)};
+      std::vector<double> wrow(n);
+      for (int s = 0; s < n; ++s) wrow[s] = 1.0 / std::max(1.0, std::max(std::fabs(b[s]), std::fabs(c[s])));
+      prog[MIX_I_ALPHA_T] = {bidiag_stage(IT, n, !low), scale_stage(g)};
+      prog[MIX_W_I] = {scale_stage(g), bidiag_stage(I1, n, low), scale_stage(wrow)};
+      prog[MIX_W_I_T] = {scale_stage(wrow), bidiag_stage(IT, n, !low), scale_stage(g)};
       if (ch == 0) {
         sweeps->meta.assign(size_t(MIX_COUNT) * 2 * 4, 0);
         sweeps->coef.assign(size_t(MIX_COUNT) * 2 * kMaxStages * 4 * kLsPad, 0.0);

@@ -36,7 +36,8 @@ PREC_NAMES = {v: k for k, v in PREC.items()}
 MIXED_MODES = {"reliable": 0, "defect": 1}
 
 MIX_KINDS = {"identity": 0, "BG": 1, "N": 2, "Ginv_Iinv": 3, "g5_IinvT_Ginv": 4, "NT": 5,
-             "G_BT_g5": 6, "Iinv": 7, "I_alpha": 8}
+             "G_BT_g5": 6, "Iinv": 7, "I_alpha": 8, "I_alpha_T": 9, "W_I": 10, "W_I_T": 11}
+SCHUR_FORMS = {"redblack": 0, "redblack1": 1, "redblack1_scaled": 2}
 
 
 class dwa_params(ctypes.Structure):
@@ -108,6 +109,10 @@ def lib():
         "dwa_cgne_solve": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats)]),
         "dwa_propagator": (c_int, [P, P, P, POINTER(dwa_solve_opts), POINTER(dwa_solve_stats), P]),
         "dwa_set_alpha": (c_int, [P, c_double]),
+        "dwa_propagator_form": (c_int, [P, c_int, P, P, POINTER(dwa_solve_opts),
+                                        POINTER(dwa_solve_stats)]),
+        "dwa_overlap_apply": (c_int, [P, c_double, P, P, POINTER(dwa_solve_opts),
+                                      POINTER(dwa_solve_stats)]),
         "dwa_alpha_sweep": (c_int, [P, POINTER(c_double), c_int, P, P, POINTER(dwa_solve_opts),
                                     POINTER(dwa_solve_stats)]),
         "dwa_propagator_adjoint": (c_int, [P, P, P, POINTER(c_double), POINTER(c_double),
@@ -422,6 +427,31 @@ class Context:
         if want_psi:
             return y1, st.as_dict(), rc, psi
         return y1, st.as_dict(), rc
+
+    def propagator_form(self, eta, form="redblack1", **kw):
+        """y_1 with the Schur system in one of the forms of Sec. 3 (dwa_propagator_form).
+        Returns (y1, stats dict, status)."""
+        torch = _torch()
+        self._check_canon(eta, (self.V, 4, 3))
+        y1 = torch.zeros((self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        f = SCHUR_FORMS[form] if isinstance(form, str) else int(form)
+        o = self.opts(**kw)
+        st = dwa_solve_stats()
+        rc = check(lib().dwa_propagator_form(self._h, f, _ptr(y1), _ptr(eta), byref(o), byref(st)),
+                   allow=(DWA_ENOCONV,))
+        return y1, st.as_dict(), rc
+
+    def overlap_apply(self, x, m, **kw):
+        """D_OV(m) x through one 5D solve on this (mass 1) context (dwa_overlap_apply).
+        Returns (D_OV(m) x, stats dict, status)."""
+        torch = _torch()
+        self._check_canon(x, (self.V, 4, 3))
+        out = torch.zeros_like(x)
+        o = self.opts(**kw)
+        st = dwa_solve_stats()
+        rc = check(lib().dwa_overlap_apply(self._h, float(m), _ptr(out), _ptr(x), byref(o), byref(st)),
+                   allow=(DWA_ENOCONV,))
+        return out, st.as_dict(), rc
 
     def propagator_adjoint(self, eta, eta_prime, want=("U", "eta", "alpha", "b", "c"), **kw):
         """Gradients of L = Re <eta', y_1> (dwa_propagator_adjoint).  Returns a dict with

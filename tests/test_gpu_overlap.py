@@ -1,0 +1,148 @@
+"""The 4D overlap operator through the 5D engine (App. A, eq.(startprop)):
+dwa_overlap_apply computes D_OV(m) x = [P^-1 D_1(1)^-1 D_1(m) P (x, 0, ..., 0)]_1 with one
+red-black CGNE solve on a context of mass 1.
+
+* against the oracle's dense D_OV(m) from the transfer matrices (per-slice b_i, c_i,
+  alpha != 1, a ragged lattice);
+* D_OV(1) = 1 and D_OV(m) = (1 - m) D_OV(0) + m (eq. after (startprop));
+* the inverse: D_OV(m) applied to the propagator y_1 = D_OV(m)^-1 eta gives eta back;
+* gamma_5-hermiticity for constant b, c;
+* with Zolotarev coefficients b_i = c_i = omega_i the Ginsparg-Wilson relation
+  gamma_5 D + D gamma_5 - 2 D gamma_5 D = 1/2 gamma_5 (1 - eps^2) holds to the accuracy of
+  the sign approximation."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import overlap, wilson, zolotarev
+from oracle.gamma import GAMMA5
+from paper_1501_04950_amd import dwa, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _ctx(dims, Ls, M5, m, alpha, b, c, U):
+    ctx = dwa.Context(dims, Ls, M5, m, alpha, b, c)
+    ctx.set_links(torch.from_numpy(U).to(gpu()))
+    return ctx
+
+
+@pytest.mark.parametrize("dims,Ls,m", [((2, 2, 2, 4), 4, 0.1), ((2, 2, 2, 6), 5, 0.3)])
+def test_overlap_apply_matches_dense_oracle(dims, Ls, m):
+    rng = np.random.default_rng(1720 + Ls)
+    b, c = rng.uniform(1.0, 2.0, Ls), rng.uniform(0.1, 0.9, Ls)
+    M5 = -1.7
+    U = synth.su3_field(dims, 0.5, 1721 + Ls)
+    V = int(np.prod(dims))
+    Dw = overlap.dense_matrix(lambda e: wilson.dw(U, e, M5, dims), (V, 4, 3))
+    D4 = overlap.overlap_D4(Dw, V, m, b, c)
+    x = synth.gaussian_source(dims, 1722)
+    ref = (D4 @ x.reshape(-1)).reshape(x.shape)
+    ctx = _ctx(dims, Ls, M5, 1.0, 0.7, b, c, U)
+    say(f"[gpu] overlap_apply {dims} Ls={Ls} m={m}")
+    out, st, rc = ctx.overlap_apply(torch.from_numpy(x).to(gpu()), m, tol=1e-13, check_every=1)
+    r = rel(out.cpu().numpy(), ref)
+    say(f"    vs dense D_OV: {r:.2e} ({st['iters']} iterations)")
+    assert rc == dwa.DWA_OK and r <= 1e-11
+    # the context must have mass 1
+    ctx_m = _ctx(dims, Ls, M5, m, 0.7, b, c, U)
+    with pytest.raises(dwa.DwaError) as e:
+        ctx_m.overlap_apply(torch.from_numpy(x).to(gpu()), m)
+    assert e.value.status == dwa.DWA_EINVAL
+    ctx.close()
+    ctx_m.close()
+
+
+C1 = synth.WORKLOADS["c1_4x4x4x4_ls8"]
+
+
+def _c1(m, b=None, c=None, Ls=None, alpha=0.8):
+    U = synth.workload_links("c1_4x4x4x4_ls8")
+    Ls = Ls or C1["Ls"]
+    b = C1["b"] if b is None else b
+    c = C1["c"] if c is None else c
+    return _ctx(C1["dims"], Ls, C1["M5"], m, alpha, b, c, U)
+
+
+def test_overlap_identities_and_inverse():
+    ctx1 = _c1(1.0)
+    dev = gpu()
+    x = torch.from_numpy(synth.gaussian_source(C1["dims"], 1730)).to(dev)
+    kw = dict(tol=1e-12, check_every=5)
+    say("[gpu] overlap identities on 4^4 Ls=8")
+    o1, _, rc = ctx1.overlap_apply(x, 1.0, **kw)
+    assert rc == dwa.DWA_OK
+    d1 = float(torch.linalg.vector_norm(o1 - x) / torch.linalg.vector_norm(x))
+    o0, _, _ = ctx1.overlap_apply(x, 0.0, **kw)
+    om_, st, _ = ctx1.overlap_apply(x, 0.3, **kw)
+    d_aff = float(torch.linalg.vector_norm(om_ - (0.7 * o0 + 0.3 * x)) / torch.linalg.vector_norm(om_))
+    say(f"    |D_OV(1) x - x| {d1:.1e}; affine in m {d_aff:.1e} ({st['iters']} iterations per apply)")
+    assert d1 <= 1e-11 and d_aff <= 1e-10
+    # inverse: D_OV(m) y_1 = eta with y_1 from the propagator of mass m
+    m = C1["m"]
+    ctxm = _c1(m)
+    y, sty, rc = ctxm.propagator(x, tol=1e-12, check_every=5)
+    back, _, rc2 = ctx1.overlap_apply(y, m, **kw)
+    d_inv = float(torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x))
+    say(f"    |D_OV(m) D_OV(m)^-1 eta - eta| / |eta| = {d_inv:.1e} ({sty['iters']} iterations)")
+    assert rc == dwa.DWA_OK and rc2 == dwa.DWA_OK and d_inv <= 1e-8
+    # gamma_5-hermiticity (constant b, c): <x2, D x> = <g5 D g5 x2, x>
+    g5 = torch.from_numpy(np.diag(GAMMA5).real.copy()).to(dev)[None, :, None]
+    x2 = torch.from_numpy(synth.gaussian_source(C1["dims"], 1731)).to(dev)
+    dx, _, _ = ctx1.overlap_apply(x, m, **kw)
+    dg, _, _ = ctx1.overlap_apply((g5 * x2).contiguous(), m, **kw)
+    lhs = complex(torch.sum(torch.conj(x2) * dx))
+    rhs = complex(torch.sum(torch.conj(g5 * dg) * x))
+    say(f"    gamma5-hermiticity {abs(lhs - rhs) / abs(lhs):.1e}")
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    ctx1.close()
+    ctxm.close()
+
+
+def test_ginsparg_wilson_with_zolotarev_coefficients():
+    """D = D_OV(0) with b_i = c_i = omega_i (Zolotarev, Ls = 12, bounds from the GPU
+    Lanczos): the Ginsparg-Wilson violation |(g5 D + D g5 - 2 D g5 D) x| / |x| =
+    |1/2 g5 (1 - eps^2) x| / |x| is at most max |1 - eps^2| / 2 <= Delta (1 + Delta / 2) with
+    Delta = 2 delta / (1 - delta) the sign bound; the constant b = c = 1 operator of the
+    same Ls violates it by far more."""
+    dev = gpu()
+    Ls = 12
+    probe = _c1(1.0, Ls=Ls)
+    lo, hi = probe.wilson_bounds(400)
+    probe.close()
+    # a margin below the estimated bottom of the spectrum
+    om, delta = dwa.zolotarev(0.98 * lo, hi, Ls, "concave")
+    Delta = 2 * delta / (1 - delta)
+    g5 = torch.from_numpy(np.diag(GAMMA5).real.copy()).to(dev)[None, :, None]
+    x = torch.from_numpy(synth.gaussian_source(C1["dims"], 1740)).to(dev)
+    kw = dict(tol=1e-13, check_every=5)
+    viol = {}
+    for name, (b, c) in (("zolotarev", (om, om)), ("b=c=1", (1.0, 1.0))):
+        ctx = _c1(1.0, b=b, c=c, Ls=Ls)
+        D = lambda v: ctx.overlap_apply(v.contiguous(), 0.0, **kw)[0]
+        Dx = D(x)
+        gw = g5 * Dx + D(g5 * x) - 2.0 * D(g5 * Dx)
+        viol[name] = float(torch.linalg.vector_norm(gw) / torch.linalg.vector_norm(x))
+        ctx.close()
+    say(f"    bounds [{lo:.4f}, {hi:.4f}], delta {delta:.1e}; GW violation {viol} "
+        f"(bound {Delta * (1 + Delta / 2):.1e})")
+    assert viol["zolotarev"] <= Delta * (1 + Delta / 2) * 1.01 + 1e-10
+    assert viol["b=c=1"] > 10 * viol["zolotarev"]
