@@ -38,9 +38,11 @@
  * solver vectors, reduction buffers); it allocates in dwa_create / dwa_set_links
  * and frees in dwa_destroy.  Operator calls do not allocate.
  *
- * Streams: all work is enqueued on the stream given to dwa_create (0 = default
- * stream).  Operator calls return without synchronising; solves synchronise on
- * their convergence checks and before returning.  A context is not thread-safe: calls
+ * Streams: operator calls enqueue their work on the stream given to dwa_create (0 =
+ * default stream) and return without synchronising.  Solves wait for that stream, run on
+ * a stream the context owns (one CG iteration is captured into a hipGraph there and
+ * replayed between the host's convergence checks), synchronise on their checks and drain
+ * before returning.  A context is not thread-safe: calls
  * on one context must not overlap (they share its workspace); different contexts are
  * independent.
  *

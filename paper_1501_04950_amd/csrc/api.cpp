@@ -129,6 +129,56 @@ int host_norm2(dwa_ctx* ctx, int prec, const void* v, double* out, size_t n = 0)
   return DWA_OK;
 }
 
+// Single-field solves run on the context's own stream, so that one CG iteration can be
+// captured into a hipGraph (capture needs a stream other than the null stream) and
+// replayed between the host's convergence checks.  Entry waits for the caller's stream;
+// exit drains the solve stream, so the caller's later work sees the results.
+struct SolveStream {
+  dwa_ctx* ctx;
+  hipStream_t saved;
+  bool on;
+  SolveStream(dwa_ctx* c) : ctx(c), saved(c->stream), on(c->cap_stream && c->stream != c->cap_stream) {
+    if (on) {
+      (void)hipStreamSynchronize(saved);
+      ctx->stream = ctx->cap_stream;
+    }
+  }
+  ~SolveStream() {
+    if (on) {
+      (void)hipStreamSynchronize(ctx->stream);
+      ctx->stream = saved;
+    }
+  }
+};
+
+// The iteration body of a CGLS between two host checks, replayed from a hipGraph (kernel
+// nodes only: the body launches kernels and nothing else), or issued eagerly with
+// DWA_SOLVE_NO_GRAPH set.  Both give bitwise the same result.
+struct BodyGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use;
+  explicit BodyGraph(dwa_ctx* ctx) : use(ctx->cap_stream && !std::getenv("DWA_SOLVE_NO_GRAPH")) {}
+  ~BodyGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  // capture body() once (it is issued, not run, during capture), then replay it
+  template <typename F>
+  int run(dwa_ctx* ctx, F&& body) {
+    if (!use) return body();
+    if (!exec) {
+      DWA_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      const int rc = body();
+      const hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+      if (rc != DWA_OK) return rc;
+      DWA_HIP(e, "end capture");
+      DWA_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    }
+    return hip_fail(hipGraphLaunch(exec, ctx->stream), "graph launch");
+  }
+};
+
 // CGLS on D_bb of precision prec with the workspace pool of that precision.
 // rhs is a field of precision prec, x one of precision xacc_prec(prec); a warm start
 // (x as given) is supported for FP64 only.  Stops when the recursive
@@ -143,6 +193,7 @@ struct CgResult {
 
 int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol, int maxiter,
          int check_every, CgResult* res, bool adj = false) {
+  SolveStream solve_stream(ctx);
   void** W = low_pool(ctx, prec);
   const bool p64 = prec == DWA_F64;
   void* r = W[p64 ? W_R : L_R];
@@ -197,6 +248,23 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
   DWA_TRY(launch_smix(ctx, prec, mixA, u, p, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
 
   const double tol2 = tol * tol;
+  // first half of an iteration: q = A p (premixed u), |q|^2; (a = gamma / |q|^2 from those
+  // partials inside update 1) x += a p ; r -= a q ; |r|^2 ; w = premix of r for A^dag
+  // (gamma = |z|^2 from the current z's partials, also inside update 1)
+  auto first_half = [&]() -> int {
+    DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
+    return launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA,
+                             bank(ctx, 2), nbZ);
+  };
+  // second half: z = A^dag r ; (beta = |z|^2 / gamma inside update 2) p = z + beta p ;
+  // u = premix of p for A
+  auto second_half = [&]() -> int {
+    DWA_TRY(applyAd(z, r, w, bank(ctx, 2), &nbZ));
+    return launch_cg_update2(ctx, prec, p, u, z, sc, adj, 1, bank(ctx, 2), nbZ);
+  };
+  // The host checks after x and r have been updated; between checks the body (second half
+  // of iteration k, first half of k + 1) is replayed from a graph.
+  BodyGraph g(ctx);
   int k = 0;
   for (;;) {
     if (k % check_every == 0 || k >= maxiter) {
@@ -215,18 +283,16 @@ int cgls(dwa_ctx* ctx, int prec, void* x, const void* rhs, bool warm, double tol
       }
       if (k >= maxiter) break;
     }
-    // q = A p (premixed u), |q|^2, a = gamma / |q|^2
-    DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
-    // (a from those partials inside update 1) x += a p ; r -= a q ; |r|^2 ;
-    // w = premix of r for A^dag
-    // (gamma = |z|^2 from the current z's partials, also inside update 1)
-    DWA_TRY(launch_cg_update1(ctx, prec, x, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA,
-                              bank(ctx, 2), nbZ));
-    // z = A^dag r ; (beta = |z|^2 / gamma inside update 2) p = z + beta p ;
-    // u = premix of p for A
-    DWA_TRY(applyAd(z, r, w, bank(ctx, 2), &nbZ));
-    DWA_TRY(launch_cg_update2(ctx, prec, p, u, z, sc, adj, 1, bank(ctx, 2), nbZ));
-    res->n_dbb += 2;
+    if (k == 0) {
+      DWA_TRY(first_half());
+      res->n_dbb += 1;
+    } else {
+      DWA_TRY(g.run(ctx, [&]() -> int {
+        DWA_TRY(second_half());
+        return first_half();
+      }));
+      res->n_dbb += 2;
+    }
     ++k;
   }
   res->iters = k;
@@ -356,6 +422,7 @@ int mixed_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_sol
 // beta = |z|^2 / gamma).  The solve stops on the FP64 residual.
 int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_solve_opts* o,
                    dwa_solve_stats* st, bool adj = false) {
+  SolveStream solve_stream(ctx);
   void** W = ctx->w64;
   void** Lw = low_pool(ctx, inner);
   void* r = Lw[L_R];
@@ -424,13 +491,33 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
   const bool trace = std::getenv("DWA_TRACE_SOLVE") != nullptr;
   double rmax = 1.0;  // |r_l| (scaled units) at the last update
   double last_rel = rel;
-  while (k < o->maxiter) {
-    // q = D_bb p ; (a from its |q|^2 partials inside update 1) x_l += a p ; r_l -= a q ;
-    // |r_l|^2 ; w = g5 I^-T G^-1 r_l
+  // first half of an iteration: q = D_bb p ; (a from its |q|^2 partials inside update 1)
+  // x_l += a p ; r_l -= a q ; |r_l|^2 ; w = g5 I^-T G^-1 r_l
+  auto first_half = [&]() -> int {
     DWA_TRY(applyA(q, p, u, bank(ctx, 0), &nbA));
-    DWA_TRY(launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA,
-                              bank(ctx, 2), nbZ));
-    ndbb += 1;
+    return launch_cg_update1(ctx, inner, xl, r, w, p, q, sc, bank(ctx, 1), &nbB, adj, 1, bank(ctx, 0), nbA,
+                             bank(ctx, 2), nbZ);
+  };
+  // second half: z = D_bb^dag r_l ; (beta = |z|^2 / gamma inside update 2) p = z + beta p ;
+  // u = B G p
+  auto second_half = [&]() -> int {
+    DWA_TRY(applyAd(z, r, w, bank(ctx, 2), &nbZ));
+    return launch_cg_update2(ctx, inner, p, u, z, sc, adj, 1, bank(ctx, 2), nbZ);
+  };
+  // between host checks the body (second half of iteration k, first half of k + 1) is
+  // replayed from a graph; a reliable update runs eagerly between two bodies
+  BodyGraph g(ctx);
+  while (k < o->maxiter) {
+    if (k == 0) {
+      DWA_TRY(first_half());
+      ndbb += 1;
+    } else {
+      DWA_TRY(g.run(ctx, [&]() -> int {
+        DWA_TRY(second_half());
+        return first_half();
+      }));
+      ndbb += 2;
+    }
     ++k;
     bool update = false, done = false;
     if (k % check_every == 0 || k >= o->maxiter) {
@@ -482,15 +569,11 @@ int reliable_solve(dwa_ctx* ctx, int inner, void* x, const void* rhs, const dwa_
         scale = new_scale;
         DWA_TRY(launch_convert(ctx, inner, r, DWA_F64, W[W_RES], n, 1.0 / scale));
         DWA_TRY(launch_smix(ctx, inner, mixAd, w, r, nullptr, 0.0, ctx->Ls, nullptr, nullptr));
-        DWA_TRY(launch_norm2(ctx, inner, r, n, bank(ctx, 1), &nbB));
+        // (|r_l|^2 is not needed here: the next update 1 sums it before any check)
         rmax = 1.0;
       }
     }
     if (done) break;
-    // z = D_bb^dag r_l ; (beta = |z|^2 / gamma inside update 2) p = z + beta p ; u = B G p
-    DWA_TRY(applyAd(z, r, w, bank(ctx, 2), &nbZ));
-    DWA_TRY(launch_cg_update2(ctx, inner, p, u, z, sc, adj, 1, bank(ctx, 2), nbZ));
-    ndbb += 1;
   }
   st->iters = k;
   st->outer = outer;
@@ -1157,6 +1240,8 @@ int dwa_create(dwa_ctx** out, const dwa_params* p, void* stream) {
   int rc = hip_fail(hipGetDevice(&ctx->device), "hipGetDevice");
   if (rc) return fail(rc);
   if ((rc = scratch_init(ctx->device))) return fail(rc);
+  if ((rc = hip_fail(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "solve stream")))
+    return fail(rc);
 
   // geometry: checkerboard <-> lexicographic and neighbour tables
   const int Lx = p->dims[0], Ly = p->dims[1], Lz = p->dims[2], Lt = p->dims[3];
@@ -1296,6 +1381,7 @@ int dwa_destroy(dwa_ctx* ctx) {
   f(ctx->d_scal);
   f(ctx->d_red);
   if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return DWA_OK;
 }

@@ -268,6 +268,8 @@ struct dwa_ctx {
   std::vector<double> b, c;
   int antiperiodic_t;
   hipStream_t stream;
+  hipStream_t cap_stream = nullptr;  // the context's own stream: single-field solves capture
+                                     // their CG iteration into a hipGraph on it
   int device;
   bool links_set = false;
 

@@ -487,6 +487,37 @@ def test_mixed_precision_bench_workload(inner, mode, delta):
     ctx.close()
 
 
+@pytest.mark.parametrize("inner,check_every", [("f64", 1), ("f64", 4), ("bf16", 5), ("f32", 3)])
+def test_solver_graph_replay_equals_eager(inner, check_every, monkeypatch):
+    """The single-field solvers replay one CG iteration from a hipGraph between host
+    checks (with the reliable updates and checks run eagerly in between); with
+    DWA_SOLVE_NO_GRAPH the same launches are issued one by one.  Every replay must give
+    what the eager launches give: y_1, the iteration count and the final residual are
+    bitwise the same, for the propagator and for its adjoint solve (gradients)."""
+    cs = case("c1_4x4x4x4_ls8")
+    ctx = cs.ctx()
+    eta = torch.from_numpy(synth.point_source(cs.dims, 0, 2, 2)).to(gpu())
+    etp = torch.from_numpy(synth.gaussian_source(cs.dims, 77)).to(gpu())
+    kw = dict(tol=1e-10, inner_prec=inner, check_every=check_every)
+    if inner != "f64":
+        kw["delta"] = 0.3 if inner == "bf16" else 0.05
+    res = {}
+    for mode in ("graph", "eager"):
+        if mode == "eager":
+            monkeypatch.setenv("DWA_SOLVE_NO_GRAPH", "1")
+        say(f"[gpu] solver {mode} {inner} check_every={check_every}")
+        y, st, rc = ctx.propagator(eta, **kw)
+        g = ctx.propagator_adjoint(eta, etp, want=("U",), **kw)
+        assert rc == dwa.DWA_OK and g["status"] == dwa.DWA_OK
+        res[mode] = (y.cpu().numpy(), st, g["U"].cpu().numpy(), g["stats"])
+    (yg, sg, ug, gg), (ye, se, ue, ge) = res["graph"], res["eager"]
+    say(f"    iters {sg['iters']} / {se['iters']}, adjoint {gg[1]['iters']} / {ge[1]['iters']}")
+    assert np.array_equal(yg, ye) and np.array_equal(ug, ue)
+    assert sg["iters"] == se["iters"] and sg["rel_resid"] == se["rel_resid"]
+    assert gg[1]["iters"] == ge[1]["iters"] and gg[1]["rel_resid"] == ge[1]["rel_resid"]
+    ctx.close()
+
+
 @pytest.mark.parametrize("inner", ["f64", "bf16"])
 def test_zero_source_gives_zero(inner):
     """eta = 0: the solve stops at once with y_1 = 0 and status ok (degenerate case)."""
