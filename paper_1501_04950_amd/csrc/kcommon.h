@@ -62,7 +62,9 @@ __device__ __forceinline__ cpx<typename S::real> ldbuf(__amdgpu_buffer_rsrc_t r,
   }
 }
 
-template <typename S>
+// AUX: the cache-policy operand of the store (0, or kStoreNT for a non-temporal store)
+constexpr int kStoreNT = 2;
+template <typename S, int AUX = 0>
 __device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
                                       cpx<typename S::real> v) {
   if constexpr (S::prec == DWA_F64) {
@@ -72,12 +74,12 @@ __device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t r, unsigned voff, u
     // soffset the imaginary half of the last store of a loop was seen overwritten by
     // the norm that followed it).  So the whole offset goes into the lane offset.
     const dwa_v2d d = {v.re, v.im};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(dwa_v4u, d), r, voff + soff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(dwa_v4u, d), r, voff + soff, 0, AUX);
   } else if constexpr (S::prec == DWA_F32) {
     const dwa_v2f f = {v.re, v.im};
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(dwa_v2u, f), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(dwa_v2u, f), r, voff, soff, AUX);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b32(pack_bf16x2(v.re, v.im), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(pack_bf16x2(v.re, v.im), r, voff, soff, AUX);
   }
 }
 
@@ -535,6 +537,17 @@ __host__ __device__ constexpr size_t hop_mix_lds_bytes(int NS, int Ls, int nf = 
          size_t(8) * NS * sizeof(unsigned);
 }
 
+// Cache policy of the fused hop's output stores.  FP64 and FP32 store non-temporally: at
+// 16^3 x 32, L_s = 16 the input field, the links and the output of an FP64 hop (201 + 75
+// + 201 MB) exceed the 256 MB Infinity Cache, and without the hint the output evicts the
+// input lines that the gathers of the neighbouring sites read again.  Measured there:
+// FP64 D_bb 478 -> 464 us (solve 466 -> 462 ms), FP32 D_bb 257 -> 248 us (FP32-inner solve
+// 264.6 -> 258.2 ms); the BF16 solve, whose fields fit, got slower (138.3 -> 140.3 ms).
+template <typename S>
+__host__ __device__ constexpr int hop_store_aux() {
+  return S::prec == DWA_BF16 ? 0 : kStoreNT;
+}
+
 // Phase 2 of hop_mix_kernel for one (site, component) of chirality CH: read the Ls
 // values from the tile, apply the fifth-dimension matrix, add the post term, store.
 template <typename S, int NS, int LSM, int MODE, int KIND, int CH, bool DENSE>
@@ -573,7 +586,7 @@ __device__ __forceinline__ double hop_mix_out(const HopDev& a, const lcpx<RealOf
       if (i < Ls) {
         cpx<R> o = v[i];
         if constexpr (MODE == 1) o = o + qc * pv[i];
-        stbuf<S>(rout, off, unsigned(i) * sstride, o);
+        stbuf<S, hop_store_aux<S>()>(rout, off, unsigned(i) * sstride, o);
         if constexpr (MODE == 1) nrm += (double)norm2(o);
       }
   }
