@@ -20,7 +20,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import mobius
-from .gamma import P_MINUS, P_PLUS, spin_apply
+from .gamma import GAMMA5, P_MINUS, P_PLUS, spin_apply
 
 
 def parity(dims) -> np.ndarray:
@@ -99,6 +99,32 @@ class RedBlack:
                 col = mobius.apply_D(None, e, p.M5, p.m, p.alpha, p.b, p.c, (1, 1, 1, 1))
                 mat[:, s * 4 + spin] = col[:, 0, :, 0].reshape(-1)
         return mat
+
+    def bg_matrix(self):
+        """(4 Ls) x (4 Ls) site matrix of the D_w parts of eq.(mobius1), index s*4 + spin:
+        block (i, j, scalar, D_{i+-}, S) contributes scalar * (b_i for D_{i+}, c_i for
+        D_{i-}) * S, so that D_alpha = D_w (this matrix) + (the parts without D_w)."""
+        p = self.p
+        mat = np.zeros((4 * p.Ls, 4 * p.Ls), dtype=np.complex128)
+        for i, j, scal, sign, spin in mobius.block_terms(p.Ls, p.m, p.alpha):
+            coef = p.b[i] if sign == "+" else p.c[i]
+            mat[4 * i:4 * i + 4, 4 * j:4 * j + 4] += scal * coef * spin
+        return mat
+
+    def mix_matrix(self, kind):
+        """The site matrix (index s*4 + spin) of a fifth-dimension mix of the red-black
+        operators, from the zero-link block I = I_1 G and BG: N = B I_1^-1 = BG I^-1 and its
+        transpose NT, G^-1 I_1^-1 = I^-1, G B^T g5 = (BG)^T g5 (all real), BG itself."""
+        Ls = self.p.Ls
+        I, BG = self.I_mat, self.bg_matrix()
+        g5 = np.kron(np.eye(Ls), GAMMA5)
+        Iinv = np.linalg.inv(I)
+        return {"identity": np.eye(4 * Ls), "BG": BG, "N": BG @ Iinv, "NT": (BG @ Iinv).T,
+                "Ginv_Iinv": Iinv, "G_BT_g5": BG.T @ g5, "I_alpha": I}[kind]
+
+    def site_apply(self, mat, psi5):
+        """A (4 Ls) x (4 Ls) site matrix (index s*4 + spin) applied at every site."""
+        return self._site_apply(mat, psi5)
 
     def _site_apply(self, mat, psi5):
         Ls = self.p.Ls

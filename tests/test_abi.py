@@ -140,6 +140,24 @@ def test_hopping_split_matches_oracle(Ls):
     assert np.linalg.norm(lhs - rhs) <= 1e-13 * np.linalg.norm(lhs)
 
 
+@pytest.mark.parametrize("Ls", [2, 3, 7])
+@pytest.mark.parametrize("kind", ["identity", "BG", "N", "NT", "Ginv_Iinv", "G_BT_g5", "I_alpha"])
+def test_mix_tables_match_oracle(Ls, kind):
+    """Every fifth-dimension matrix the kernels apply (per chirality, Ls x Ls) equals the
+    oracle's site matrix of the same operator, built from the block list of eq.(mobius1),
+    and acts as the identity on spin within each chirality."""
+    pr = _params(Ls, 30 + Ls, 0.8)
+    op = redblack.Params.make(pr["dims"], Ls, pr["M5"], pr["m"], pr["alpha"], pr["b"], pr["c"])
+    O = redblack.RedBlack(synth.unit_field(pr["dims"]), op).mix_matrix(kind).reshape(Ls, 4, Ls, 4)
+    M = dwa.dwa_debug_smatrix(kind=kind, **pr)
+    for spin in range(4):
+        ch = 0 if spin < 2 else 1
+        assert np.abs(O[:, spin, :, spin] - M[ch]).max() < 1e-13
+        for other in range(4):
+            if other != spin:
+                assert np.abs(O[:, spin, :, other]).max() == 0.0
+
+
 @pytest.mark.parametrize("Ls", [2, 6])
 def test_matrix_identities(Ls):
     """N = B I_1^-1, G^-1 I_1^-1 = (I_1 G)^-1, the adjoint premixes, from the same B, G, I_1."""

@@ -555,18 +555,16 @@ def test_error_paths():
 
 
 @pytest.mark.parametrize("name", ["ragged_2x2x2x6_ls2", "c1_4x4x4x4_ls8", "ls20_4x2x2x4"])
-@pytest.mark.parametrize("kind", ["identity", "N", "G_BT_g5"])
+@pytest.mark.parametrize("kind", ["identity", "N", "NT", "Ginv_Iinv", "G_BT_g5"])
 def test_single_hop_launch(name, kind):
     """dwa_apply_hop: out = M_kind H_rb x_b with H the hopping sum of eq.(wilson) without
-    its -1/2: on red sites D_w x_b = -1/2 H_rb x_b for a black-only x_b."""
+    its -1/2 (on red sites D_w x_b = -1/2 H_rb x_b for a black-only x_b), and M_kind built
+    from the oracle's own site matrices of eq.(mobius1)."""
     cs = case(name)
     ctx = cs.ctx()
     x = cs.black_field(31)
     h = -2.0 * wilson.dw(cs.U, x, cs.M5, cs.dims) * cs.oracle().red
-    M = dwa.dwa_debug_smatrix(cs.dims, cs.Ls, cs.M5, cs.m, cs.alpha, cs.b, cs.c, kind)
-    ref = np.empty_like(h)
-    ref[:, :, :2] = np.einsum("ij,jxsc->ixsc", M[0], h[:, :, :2])
-    ref[:, :, 2:] = np.einsum("ij,jxsc->ixsc", M[1], h[:, :, 2:])
+    ref = cs.oracle().site_apply(cs.oracle().mix_matrix(kind), h)
     xt = torch.from_numpy(x).to(gpu())
     say(f"[gpu] apply_hop {name} {kind}")
     out = ctx.apply_hop(ctx.pack(xt, 0, "f64"), 1, kind, "f64")

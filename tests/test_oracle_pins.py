@@ -432,3 +432,29 @@ def test_redblack_matches_unpreconditioned_and_dense():
     psi_lu = np.linalg.solve(dense, rho.reshape(-1)).reshape(rho.shape)
     assert rel(psi, psi_lu) < 1e-10
     assert rel(psi_full, psi_lu) < 1e-10
+
+
+@pytest.mark.parametrize("Ls", [2, 3, 6])
+def test_bg_matrix_splits_D_alpha(Ls):
+    """eq.(mobius1) with D_w = (4 + M5) - H/2 (eq.(wilson)): the oracle's D_w-coefficient
+    site matrix BG satisfies D_alpha psi = D_w (BG psi) + (I - (4 + M5) BG) psi, with I the
+    zero-link site block, for random per-slice b, c (Ls = 2 sums two blocks per entry).
+    Also the structure eq.(coeff) fixes: BG is real, block-diagonal in chirality, and at
+    alpha = 1 with b = c = 1 its diagonal is 1 on every spin."""
+    dims = (4, 2, 2, 2)
+    rng = np.random.default_rng(40 + Ls)
+    b, c = rng.uniform(1.0, 2.0, Ls), rng.uniform(0.1, 0.9, Ls)
+    p = redblack.Params.make(dims, Ls, -1.7, 0.06, 0.7, b, c)
+    U = synth.su3_field(dims, 0.5, 41)
+    rb = redblack.RedBlack(U, p)
+    BG = rb.bg_matrix()
+    psi = synth.gaussian_field5(dims, Ls, 42)
+    bgpsi = rb.site_apply(BG, psi)
+    rhs = wilson.dw(U, bgpsi, p.M5, dims) + rb.site_apply(rb.I_mat - (4 + p.M5) * BG, psi)
+    assert rel(rhs, rb.D(psi)) < 1e-13
+    assert np.abs(BG.imag).max() == 0.0
+    B4 = BG.reshape(Ls, 4, Ls, 4)
+    assert np.abs(B4[:, :2, :, 2:]).max() == 0.0 and np.abs(B4[:, 2:, :, :2]).max() == 0.0
+    p1 = redblack.Params.make(dims, Ls, -1.7, 0.06, 1.0, np.ones(Ls), np.ones(Ls))
+    d1 = np.diag(redblack.RedBlack(U, p1).bg_matrix())
+    assert np.allclose(d1, 1.0, atol=1e-15)
