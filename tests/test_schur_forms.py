@@ -61,6 +61,28 @@ def test_forms_share_the_solution(bc):
         assert np.linalg.norm(phi - rb.Dbb(x)) <= 1e-11 * np.linalg.norm(phi)
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_row_weights_bound_every_row(seed):
+    """The row scaling after eq.(redblack1): each row of the scaled operator keeps its D_w
+    coefficients at most one, and rows already within one are left alone.  The
+    coefficients of row s are read off the oracle's D_w-coefficient matrix of the block
+    list of eq.(mobius1) (alpha = 1, so that row's largest entry is max(b_s, c_s)), with
+    rows dominated by b and rows dominated by c both present."""
+    dims, Ls = (2, 2, 2, 2), 8
+    rng = np.random.default_rng(1760 + seed)
+    b, c = rng.uniform(0.3, 2.0, Ls), rng.uniform(0.3, 2.5, Ls)
+    b[0], c[0] = 1.6, 2.2   # c dominates, above one
+    b[1], c[1] = 2.1, 0.4   # b dominates, above one
+    b[2], c[2] = 0.7, 0.9   # within one
+    p = redblack.Params.make(dims, Ls, -1.7, 0.1, 1.0, b, c)
+    rb = redblack.RedBlack(synth.unit_field(dims), p)
+    w = rb.row_weights()
+    rowmax = np.abs(rb.bg_matrix()).reshape(Ls, 4, 4 * Ls).max(axis=(1, 2))
+    assert np.all(w * rowmax <= 1.0 + 1e-14)
+    assert np.allclose((w * rowmax)[rowmax > 1.0], 1.0, atol=1e-14)
+    assert np.all(w[rowmax <= 1.0] == 1.0)
+
+
 @pytest.mark.skipif(not __import__("os").path.exists(dwa.LIB_PATH), reason="libdwa.so not built")
 def test_library_tables_for_the_forms():
     """Kinds 9..11 of dwa_debug_smatrix: (I_1 G)^T, W I_1 G and its transpose, with W the
