@@ -742,17 +742,21 @@ def overlap_study(torch, dwa, Ud, w, eta, y_mixed):
 
 def small_solves(torch, dwa, synth, dev):
     """Time to solution of the two small workloads (launch-latency bound): the 4^4, L_s =
-    8 point source (FP64) and the 8^3 x 16, L_s = 12 point source (FP64 and FP32 inner),
-    tol 1e-10, median of 5 after a warm-up."""
+    8 point source (FP64; a host check every iteration, which stops at the oracle's
+    iteration, and every 5, which replays 5 iterations from the graph per check) and the
+    8^3 x 16, L_s = 12 point source (FP64 and FP32 inner), tol 1e-10, median of 5 after a
+    warm-up."""
     out = {}
-    for name, inners in (("c1_4x4x4x4_ls8", ("f64",)), ("c2_8x8x8x16_ls12", ("f64", "f32"))):
+    for name, inners in (("c1_4x4x4x4_ls8", ("f64", "f64_check5")), ("c2_8x8x8x16_ls12", ("f64", "f32"))):
         w = synth.WORKLOADS[name]
         ctx = dwa.Context(w["dims"], w["Ls"], w["M5"], w["m"], 1.0, w["b"], w["c"])
         ctx.set_links(torch.from_numpy(synth.workload_links(name)).to(dev))
         eta = torch.from_numpy(synth.point_source(w["dims"], 0, 0, 0)).to(dev)
         res = {}
-        for inner in inners:
-            kw = dict(tol=1e-10, inner_prec=inner, check_every=1 if name.startswith("c1") else 5)
+        for key in inners:
+            inner = key.split("_")[0]
+            check = 1 if key == "f64" and name.startswith("c1") else 5
+            kw = dict(tol=1e-10, inner_prec=inner, check_every=check)
             if inner != "f64":
                 kw["delta"] = 0.05
             ctx.propagator(eta, **kw)
@@ -763,9 +767,9 @@ def small_solves(torch, dwa, synth, dev):
                 y, st, rc = ctx.propagator(eta, **kw)
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
-            res[inner] = {"time_s": round(statistics.median(ts), 5), "iters": st["iters"],
-                          "rel_resid": st["rel_resid"], "status": rc, "check_every": kw["check_every"]}
-            log(f"  {name} {inner}: {res[inner]['time_s'] * 1e3:.2f} ms, {st['iters']} iters")
+            res[key] = {"time_s": round(statistics.median(ts), 5), "iters": st["iters"],
+                        "rel_resid": st["rel_resid"], "status": rc, "check_every": kw["check_every"]}
+            log(f"  {name} {key}: {res[key]['time_s'] * 1e3:.2f} ms, {st['iters']} iters")
         out[name] = res
         ctx.close()
     return out
