@@ -192,7 +192,11 @@ def main():
         log(f"  FP64: {fp64['time_s']:.3f} s, {st64['iters']} iters, resid {st64['rel_resid']:.2e}")
 
     # --- mixed-precision steps (timed) ------------------------------------------------
-    delta = args.delta if args.delta is not None else (0.3 if args.inner == "bf16" else 0.02)
+    # delta: the reliable-update threshold, or the inner tolerance of a defect-correction
+    # restart (both picked by sweeps on this workload)
+    default_delta = {("reliable", "bf16"): 0.3, ("reliable", "f32"): 0.02,
+                     ("defect", "bf16"): 0.01, ("defect", "f32"): 0.01}
+    delta = args.delta if args.delta is not None else default_delta[(args.mixed_mode, args.inner)]
     kw = dict(tol=args.tol, inner_prec=args.inner, delta=delta, check_every=args.check_every,
               mixed_mode=args.mixed_mode)
     for i in range(args.warmup):
@@ -211,6 +215,22 @@ def main():
         log(f"step {i}: {times[-1]:.3f} s, iters {st['iters']} outer {st['outer']} "
             f"resid {st['rel_resid']:.2e} status {rc}")
     mixed_s = statistics.mean(times)
+    # the other FP64 outer scheme on the same solve: restarted defect correction beside
+    # reliable updates (or the reverse), median of 3 after a warm-up
+    other_mode = "defect" if args.mixed_mode == "reliable" else "reliable"
+    okw = dict(kw, mixed_mode=other_mode, delta=default_delta[(other_mode, args.inner)])
+    ctx.propagator(eta_d, **okw)
+    ots = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ost, orc = ctx.propagator(eta_d, **okw)
+        torch.cuda.synchronize()
+        ots.append(time.perf_counter() - t0)
+    other = {"mixed_mode": other_mode, "delta": okw["delta"], "time_s": round(statistics.median(ots), 4),
+             "iters": ost["iters"], "outer": ost["outer"], "rel_resid": ost["rel_resid"], "status": orc}
+    log(f"other outer scheme ({other_mode}, delta {okw['delta']}): {other['time_s']:.3f} s, "
+        f"iters {ost['iters']} outer {ost['outer']}")
     y_err = None
     if y64 is not None:
         y_err = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
@@ -333,6 +353,7 @@ def main():
                    "outer": "f64 reliable updates" if args.mixed_mode == "reliable" else "f64 defect correction",
                    "inner": args.inner, "delta": delta,
                    "mixed_mode": args.mixed_mode},
+        "other_outer_scheme": other,
         "mixed": {"time_s": round(mixed_s, 4), "iters": stats[-1]["iters"],
                   "outer": stats[-1]["outer"], "rel_resid": stats[-1]["rel_resid"],
                   "y1_rel_diff_vs_fp64": y_err},
