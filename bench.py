@@ -434,6 +434,17 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
 
     r32 = solve_both(dict(tol=args.tol, inner_prec="f32", delta=0.1, check_every=args.check_every), "FP32")
     r16 = solve_both(dict(tol=args.tol, inner_prec="bf16", delta=0.3, check_every=args.check_every), "BF16")
+    # the same 36 systems batched in plain FP64 (one timed run): the time the mixed
+    # batches are measured against at equal accuracy
+    log("batch: 3 lattices x 12 sources, FP64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, sts64, rc64 = dwa.propagator_multi(batches, tol=args.tol, inner_prec="f64", check_every=args.check_every)
+    torch.cuda.synchronize()
+    f64_batched = {"batched_s": round(time.perf_counter() - t0, 4), "status": rc64,
+                   "iters": [max(s["iters"] for s in st) for st in sts64],
+                   "max_rel_resid": max(s["rel_resid"] for st in sts64 for s in st)}
+    log(f"  FP64 batched: {f64_batched['batched_s']:.3f} s")
     # batched D_bb, 12 FP32 fields on the largest lattice
     ctx = batches[2][0]
     x = torch.stack([ctx.half_field("f32") for _ in range(12)]).contiguous()
@@ -478,6 +489,7 @@ def batch_bench(torch, dwa, synth, dev, stream, args):
                        f"spread {bw['spread']}, alpha {bw['alpha']}, m {bw['m']}, tol {args.tol}"}
     out.update(r32)  # FP32 inner at the top level, as before
     out["bf16_inner"] = r16
+    out["f64"] = f64_batched
     out["dbb_batch"] = dbb
     return out
 
