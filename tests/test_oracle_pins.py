@@ -383,11 +383,13 @@ def test_mass_one_gives_identity():
     assert rel(y, eta) < 1e-11
 
 
-def test_free_field_momentum_closed_form():
+@pytest.mark.parametrize("M5", [-1.8, 1.8])
+def test_free_field_momentum_closed_form(M5):
     """U = 1, antiperiodic t: y_1 for a plane-wave source equals the polar form
-    D_OV(p)^-1 of eq.(polar)/(argument) applied to the spinor."""
+    D_OV(p)^-1 of eq.(polar)/(argument) applied to the spinor, for either sign of M5
+    (the API takes the M5 of eq.(wilson) literally)."""
     dims, Ls = (4, 4, 2, 4), 6
-    p_ = redblack.Params.make(dims, Ls, -1.8, 0.1, 0.8, 1.5, 0.5)
+    p_ = redblack.Params.make(dims, Ls, M5, 0.1, 0.8, 1.5, 0.5)
     mom = [2 * np.pi * 1 / 4, 0.0, np.pi, 3 * np.pi / 4]
     x = _coords(dims)
     phase = np.exp(1j * sum(mom[k] * x[k] for k in range(4)))
@@ -398,6 +400,21 @@ def test_free_field_momentum_closed_form():
     dov = overlap.overlap_tanh_spin(overlap.free_dw(mom, p_.M5), p_.m, 1.5, 0.5, Ls)
     expect = phase[:, None, None] * np.linalg.solve(dov, u)[None]
     assert rel(y, expect) < 1e-10
+
+
+@pytest.mark.parametrize("M5,limit", [(-1.8, "m"), (1.8, "one")])
+def test_free_overlap_zero_momentum_by_sign_of_M5(M5, limit):
+    """The reading of the sign of M5: at p = 0 the free D_w of eq.(wilson) is M5 itself, so
+    gamma_5 D_w has the sign of M5 and, as L_s grows, the sign function of eq.(polar)
+    tends to -gamma_5 (M5 < 0: D_OV(0) -> m, a light mode) or +gamma_5 (M5 > 0: D_OV(0) ->
+    1, no light mode).  Closed form at L_s = 64 and 128 (b = 1.5, c = 0.5, m = 0.05)."""
+    m = 0.05
+    Dw0 = overlap.free_dw([0.0, 0.0, 0.0, 0.0], M5)
+    assert np.allclose(Dw0, M5 * np.eye(4))
+    for Ls, tol in ((64, 5e-3), (128, 1e-5)):
+        dov = overlap.overlap_tanh_spin(Dw0, m, 1.5, 0.5, Ls)
+        target = m * np.eye(4) if limit == "m" else np.eye(4)
+        assert np.abs(dov - target).max() < tol, (Ls, np.abs(dov - target).max())
 
 
 def test_free_field_zero_momentum_golden():
