@@ -33,6 +33,8 @@ CASES = {
     "ls16_ragged_2x2x2x6": ((2, 2, 2, 6), 16, -1.8, 0.05, 0.8, 1.5, 0.5),
     "ls16_4x4x4x4": ((4, 4, 4, 4), 16, -1.7, 0.03, 1.2, None, None),
     "ls12_ragged_2x2x2x6": ((2, 2, 2, 6), 12, -1.8, 0.05, 0.7, None, None),
+    # the other sign of M5 (taken literally in the (4 + M5) of eq.(wilson))
+    "posM5_4x2x2x4_ls6": ((4, 2, 2, 4), 6, 1.8, 0.05, 0.9, None, None),
 }
 
 
@@ -328,13 +330,15 @@ def test_cgne_matches_oracle_cgls():
     ctx.close()
 
 
-def test_propagator_matches_oracle():
-    """y_1 for a point source (site 0, spin 0, colour 0) on the 4^4, Ls=8 lattice."""
-    cs = case("c1_4x4x4x4_ls8")
+@pytest.mark.parametrize("name", ["c1_4x4x4x4_ls8", "posM5_4x2x2x4_ls6"])
+def test_propagator_matches_oracle(name):
+    """y_1 for a point source (site 0, spin 0, colour 0) on the 4^4, Ls=8 lattice, and
+    with M5 = +1.8 on 4x2x2x4, Ls = 6."""
+    cs = case(name)
     eta = synth.point_source(cs.dims, 0, 0, 0)
     y_ref, info = redblack.propagator(cs.U, eta, cs.p, tol=1e-12)
     ctx = cs.ctx()
-    say("[gpu] propagator c1 f64 tol 1e-12")
+    say(f"[gpu] propagator {name} f64 tol 1e-12")
     y, st, rc = ctx.propagator(torch.from_numpy(eta).to(gpu()), tol=1e-12, check_every=1)
     yg = y.cpu().numpy()
     r = rel(yg, y_ref)
