@@ -475,3 +475,32 @@ def test_bg_matrix_splits_D_alpha(Ls):
     p1 = redblack.Params.make(dims, Ls, -1.7, 0.06, 1.0, np.ones(Ls), np.ones(Ls))
     d1 = np.diag(redblack.RedBlack(U, p1).bg_matrix())
     assert np.allclose(d1, 1.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.7])
+def test_free_5d_solution_per_momentum(alpha):
+    """T6 (ii): with U = 1 a 5D plane-wave right-hand side rho(x, s) = exp(ip.x) r_s stays a
+    plane wave, and eq.(mobius1) acts on its 4 L_s spin-slice amplitudes as the dense
+    momentum-space matrix D_alpha(p): block (i, j, scalar, D_{i+-}, S) becomes
+    scalar * (coef_i D_w(p) +- 1) S with D_w(p) the free 4x4 matrix of eq.(wilson).  The
+    red-black Schur solve (eq.(redblack), prep, CGLS on D_bb, reconstruction) returns
+    exp(ip.x) D_alpha(p)^-1 r, per-slice b, c random, antiperiodic t."""
+    dims, Ls = (4, 2, 2, 4), 5
+    rng = np.random.default_rng(171)
+    b, c = rng.uniform(1.0, 2.0, Ls), rng.uniform(0.1, 0.9, Ls)
+    p = redblack.Params.make(dims, Ls, -1.6, 0.07, alpha, b, c)
+    mom = [2 * np.pi / 4, np.pi, 0.0, 3 * np.pi / 4]
+    Dp = overlap.free_dw(mom, p.M5)
+    A = np.zeros((4 * Ls, 4 * Ls), dtype=np.complex128)
+    for i, j, scal, sign, spin in mobius.block_terms(Ls, p.m, p.alpha):
+        coef = b[i] if sign == "+" else c[i]
+        A[4 * i:4 * i + 4, 4 * j:4 * j + 4] += scal * (coef * Dp + (1.0 if sign == "+" else -1.0) * np.eye(4)) @ spin
+    x = _coords(dims)
+    phase = np.exp(1j * sum(mom[k] * x[k] for k in range(4)))
+    r = rng.standard_normal((Ls, 4, 3)) + 1j * rng.standard_normal((Ls, 4, 3))
+    rho = phase[None, :, None, None] * r[:, None]
+    rb = redblack.RedBlack(synth.unit_field(dims), p)
+    xb, info = redblack.cgls(rb.Dbb, rb.Dbb_dag, rb.schur_rhs(rho), 1e-13, 10000)
+    psi = rb.black * xb + rb.reconstruct_red(rb.black * xb, rho)
+    amp = np.linalg.solve(A, r.reshape(4 * Ls, 3)).reshape(Ls, 4, 3)
+    assert rel(psi, phase[None, :, None, None] * amp[:, None]) < 1e-11
