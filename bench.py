@@ -512,9 +512,12 @@ def make_roofline(kern, tuning, inner, dims, Ls, S, L):
     """Roofline record of the dominant kernel (the first hop of D_bb in the inner
     precision, hop_mix_kernel MODE 0 with the N mix), against both resources it can be
     bound by: HBM bytes (algorithmic 2S + L per launch, timed as inside a solve and cold)
-    and VALU issue (the committed SQ_INSTS_VALU count per launch, when it was taken on
-    the kernel source built here).  `bound` is the resource closer to its peak; for
-    "alu", achieved / peak are algorithmic FP32 TFLOP/s against 78.6."""
+    and VALU arithmetic (algorithmic flops; beside them the VALU issue fraction from the
+    committed SQ_INSTS_VALU count per launch, when it was taken on the kernel source built
+    here).  `bound` follows the classical roofline: "alu" when the kernel's arithmetic
+    intensity (algorithmic flops per algorithmic byte) exceeds the machine balance (FP32
+    vector peak / HBM peak), else "hbm"; for "alu", achieved / peak are algorithmic FP32
+    TFLOP/s against 78.6."""
     V = int(np.prod(dims))
     dom = kern[inner]
     ns_dom = tuning[inner]["ns"]
@@ -533,9 +536,13 @@ def make_roofline(kern, tuning, inner, dims, Ls, S, L):
                     "hop_frac_cold": round(kern[p]["hop_cold_gbs"] / HBM_PEAK_GBS, 4),
                     "dbb_frac": round(kern[p]["dbb_gbs"] / HBM_PEAK_GBS, 4),
                     "dbb_dag_frac": round(kern[p]["dbb_dag_gbs"] / HBM_PEAK_GBS, 4)} for p in kern}
-    vf = alu["valu_issue_frac"]
-    bound = "alu" if vf is not None and vf > hbm_frac else "hbm"
+    bytes_launch = 2 * S[inner] + L[inner]
+    intensity = flops / bytes_launch
+    balance = FP32_FMA_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    bound = "alu" if intensity > balance else "hbm"
     rec = {"bound": bound,
+           "arithmetic_intensity_flop_per_byte": round(intensity, 2),
+           "machine_balance_flop_per_byte": round(balance, 2),
            "kernel": f"hop_mix_kernel<{inner.upper()},{ns_dom},{Ls},0> (fused Wilson hop + N mix)",
            "traffic": measured_traffic(name),
            "bytes_per_launch": 2 * S[inner] + L[inner],
