@@ -362,7 +362,8 @@ int dwa_propagator_batch(dwa_ctx *ctx, int nrhs, void *y1, const void *eta,
 
 /* dwa_propagator_batch over several contexts (lattices of different sizes) in one
  * solve: nrhs[i] sources of ctxs[i] in eta[i] -> y1[i]; one hipGraph holds the CGNE
- * iteration of every context.  All contexts must be on one device and have reserved
+ * iteration of every context that still has a live field (it is captured again when a
+ * context's fields have all stopped).  All contexts must be on one device and have reserved
  * their batches; the work runs on the first context's batch stream after every
  * context's stream has drained.  stats receives sum(nrhs) entries in context order. */
 int dwa_propagator_multi(dwa_ctx *const *ctxs, int nctx, const int *nrhs, void *const *y1,
