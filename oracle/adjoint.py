@@ -80,22 +80,24 @@ def _dw_part_terms(x5, m, alpha, p):
     return out
 
 
-def adjoint_field(U, eta_p, p: redblack.Params, tol=1e-13, maxiter=200000):
-    """lambda with D_alpha(m)^dag lambda = E^dag eta', by CGLS on the full 5D system
-    (no red-black), so it is independent of the Schur algebra."""
+def adjoint_field(U, eta_p, p: redblack.Params, tol=1e-13, maxiter=200000, f5=None):
+    """lambda with D_alpha(m)^dag lambda = E^dag eta' (or = f5, a general 5D cotangent,
+    when given), by CGLS on the full 5D system (no red-black), so it is independent of
+    the Schur algebra."""
     rb = redblack.RedBlack(U, p)
-    f = extraction_adjoint(eta_p, p.Ls)
+    f = extraction_adjoint(eta_p, p.Ls) if f5 is None else f5
     lam, info = redblack.cgls(rb.D_dag, rb.D, f, tol, maxiter)
     return lam, info
 
 
-def gradients(U, eta, eta_p, p: redblack.Params, tol=1e-13):
-    """dL with respect to the links, eta, alpha, b_i and c_i.  Returns a dict with
-    'U' (4, V, 3, 3), 'eta' (V, 4, 3), 'alpha' (float), 'b' and 'c' (Ls,) and the
-    forward psi and adjoint lambda."""
+def gradients(U, eta, eta_p, p: redblack.Params, tol=1e-13, f5=None):
+    """dL with respect to the links, eta, alpha, b_i and c_i, for L = Re <eta', y_1> (or,
+    with f5 given, for L = Re <f5, psi> of the whole 5D solution, whose alpha derivative
+    does not vanish).  Returns a dict with 'U' (4, V, 3, 3), 'eta' (V, 4, 3), 'alpha'
+    (float), 'b' and 'c' (Ls,) and the forward psi and adjoint lambda."""
     Ls, dims = p.Ls, p.dims
     _, _, psi = redblack.propagator(U, eta, p, tol=tol, return_psi=True)
-    lam, _ = adjoint_field(U, eta_p, p, tol=tol)
+    lam, _ = adjoint_field(U, eta_p, p, tol=tol, f5=f5)
     pb = source5(eta, Ls)
     dwf = lambda x: dw(U, x, p.M5, dims, p.antiperiodic_t)
 

@@ -114,3 +114,23 @@ def test_adjoint_field_solves_adjoint_system(asym):
     # and f pairs with psi as the extraction does: Re <f, psi> = Re <eta', y_1>
     y1 = redblack.extract_y1(g["psi"])
     assert abs(np.vdot(f.ravel(), g["psi"].ravel()) - np.vdot(eta_p.ravel(), y1.ravel())) < 1e-12
+
+
+def test_alpha_gradient_formula_on_a_5d_loss(asym):
+    """The alpha term of the adjoint gradient, on a loss whose alpha derivative does not
+    vanish: L5 = Re <f5, psi> of the whole 5D solution of D_alpha psi = D_1(1) P b
+    (rho does not depend on alpha, eq.(tosolve)).  The oracle's dL5/dalpha (lambda from
+    D_alpha^dag lambda = f5) equals central finite differences of L5 in alpha, and is
+    far from zero, so its sign is pinned (for y_1-losses it is zero, eq.(tosolve1))."""
+    U, p, eta, eta_p, _ = asym
+    f5 = synth.gaussian_field5(DIMS, LS, 9)
+    g = adjoint.gradients(U, eta, eta_p, p, f5=f5)
+
+    def L5(d):
+        q = p.with_(alpha=p.alpha + d)
+        _, _, psi = redblack.propagator(U, eta, q, tol=1e-13, return_psi=True)
+        return float(np.vdot(f5.reshape(-1), psi.reshape(-1)).real)
+
+    fd = _fd(L5)
+    assert abs(fd) > 1e-2
+    _close(fd, g["alpha"], abs(fd))

@@ -329,16 +329,18 @@ def test_source_lives_on_the_walls():
     assert np.abs(rho[1:-1]).max() == 0.0
 
 
-def test_y1_matches_transfer_matrix_overlap():
+@pytest.mark.parametrize("Ls", [4, 5])
+def test_y1_matches_transfer_matrix_overlap(Ls):
     """App. A/B: y_1 = D_OV(m)^-1 eta, with D_OV built densely from
-    S = S_1 ... S_Ls, S_i = -Q_i-^-1 Q_i+, for per-slice b_i, c_i and alpha != 1.
+    S = S_1 ... S_Ls, S_i = -Q_i-^-1 Q_i+, for per-slice b_i, c_i and alpha != 1 (an odd
+    L_s as well, where the sign of S_i survives the product).
 
     The product of transfer matrices spans many decades when some eigenvalue of
     the Moebius kernel approaches 1, which would make a dense check meaningless
     in FP64; the parameters keep cond(S) near 1e5 so the identity is checked to
     rounding.  The reversed product S_Ls ... S_1 must fail: the check sees the
     order of the slices."""
-    dims, Ls = (2, 2, 2, 2), 4
+    dims = (2, 2, 2, 2)
     vol = synth.volume(dims)
     U = synth.su3_field(dims, 0.5, 101)
     rng = np.random.default_rng(100)
