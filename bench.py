@@ -164,6 +164,9 @@ def main():
         del ins, outs, reds
         torch.cuda.empty_cache()
 
+    stream_gbs = stream_reference_gbs(torch, dev)
+    log(f"  streaming reference (torch add, 3 x 256 MiB): {stream_gbs:.0f} GB/s")
+
     if args.copy_probe:
         a = torch.empty(512 * 2**20 // 4, dtype=torch.float32, device=dev).normal_()
         b = torch.empty_like(a)
@@ -333,7 +336,7 @@ def main():
             c1_gpu = {"gpu_s": g["time_s"], "gpu_iters": g["iters"]}
         cpu = cpu_baseline(U, dims, Ls, w, args.alpha, fp64, c1_gpu)
 
-    roofline = make_roofline(kern, tuning, args.inner, dims, Ls, S, L)
+    roofline = make_roofline(kern, tuning, args.inner, dims, Ls, S, L, stream_gbs)
     result = {
         "metric": METRIC,
         "value": round(mixed_s, 4),
@@ -508,7 +511,30 @@ VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 FP32_FMA_PEAK_TFLOPS = 2 * VALU_LANE_OPS_PEAK / 1e12
 
 
-def make_roofline(kern, tuning, inner, dims, Ls, S, L):
+def stream_reference_gbs(torch, dev, reps=20):
+    """HBM bandwidth a plain streaming kernel reaches here: torch.add over three FP32
+    tensors of 256 MiB (two read, one written; 768 MiB, beyond the 256 MB Infinity Cache),
+    bytes moved / mean launch time over `reps` launches.  Context for the HBM fractions,
+    which stay against the 8 TB/s peak."""
+    n = 256 * 2**20 // 4
+    a = torch.empty(n, dtype=torch.float32, device=dev).uniform_()
+    b = torch.empty_like(a).uniform_()
+    c = torch.empty_like(a)
+    for _ in range(3):
+        torch.add(a, b, out=c)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(a, b, out=c)
+    e1.record()
+    e1.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 3 * n * 4 / s / 1e9
+
+
+def make_roofline(kern, tuning, inner, dims, Ls, S, L, stream_gbs=None):
     """Roofline record of the dominant kernel (the first hop of D_bb in the inner
     precision, hop_mix_kernel MODE 0 with the N mix), against both resources it can be
     bound by: HBM bytes (algorithmic 2S + L per launch, timed as inside a solve and cold)
@@ -517,7 +543,8 @@ def make_roofline(kern, tuning, inner, dims, Ls, S, L):
     here).  `bound` follows the classical roofline: "alu" when the kernel's arithmetic
     intensity (algorithmic flops per algorithmic byte) exceeds the machine balance (FP32
     vector peak / HBM peak), else "hbm"; for "alu", achieved / peak are algorithmic FP32
-    TFLOP/s against 78.6."""
+    TFLOP/s against 78.6.  With stream_gbs (stream_reference_gbs) the HBM record also
+    gives the in-solve hop and every precision's D_bb as a fraction of that rate."""
     V = int(np.prod(dims))
     dom = kern[inner]
     ns_dom = tuning[inner]["ns"]
@@ -536,6 +563,9 @@ def make_roofline(kern, tuning, inner, dims, Ls, S, L):
                     "hop_frac_cold": round(kern[p]["hop_cold_gbs"] / HBM_PEAK_GBS, 4),
                     "dbb_frac": round(kern[p]["dbb_gbs"] / HBM_PEAK_GBS, 4),
                     "dbb_dag_frac": round(kern[p]["dbb_dag_gbs"] / HBM_PEAK_GBS, 4)} for p in kern}
+    if stream_gbs:
+        for p in kern:
+            per_prec[p]["dbb_frac_of_stream_ref"] = round(kern[p]["dbb_gbs"] / stream_gbs, 4)
     bytes_launch = 2 * S[inner] + L[inner]
     intensity = flops / bytes_launch
     balance = FP32_FMA_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
@@ -549,7 +579,9 @@ def make_roofline(kern, tuning, inner, dims, Ls, S, L):
            "timing": "HIP events on the library stream, input written just before (as in the solve)",
            "hbm": {"achieved_gbs": round(dom["hop_gbs"], 1), "frac": round(hbm_frac, 4),
                    "achieved_cold_gbs": round(dom["hop_cold_gbs"], 1),
-                   "frac_cold": round(dom["hop_cold_gbs"] / HBM_PEAK_GBS, 4)},
+                   "frac_cold": round(dom["hop_cold_gbs"] / HBM_PEAK_GBS, 4),
+                   "stream_ref_gbs": round(stream_gbs, 1) if stream_gbs else None,
+                   "frac_of_stream_ref": round(dom["hop_gbs"] / stream_gbs, 4) if stream_gbs else None},
            "alu": alu,
            "per_precision": per_prec}
     if bound == "alu":
