@@ -287,14 +287,21 @@ def main():
                  "y1_max_rel_diff_across_alpha": spread}
         log(f"  iters {iters}; best alpha {alphas[best]} ratio {ratio:.3f}; y1 spread {spread:.1e}")
         del ys
-        # the mixed-precision solve again at the best alpha (same y_1, fewer iterations)
+        # the mixed-precision solve again at the best alpha (same y_1, fewer iterations):
+        # a warm-up, then the median of 3, as for the other solve times
         ctx.set_alpha(alphas[best])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        yb, stb, rcb = ctx.propagator(eta_d, **kw)
-        torch.cuda.synchronize()
+        ctx.propagator(eta_d, **kw)
+        tb = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            yb, stb, rcb = ctx.propagator(eta_d, **kw)
+            torch.cuda.synchronize()
+            tb.append(time.perf_counter() - t0)
         sweep["mixed_at_best_alpha"] = {
-            "alpha": alphas[best], "time_s": round(time.perf_counter() - t0, 4),
+            "alpha": alphas[best], "time_s": round(statistics.median(tb), 4),
+            "runs_s": [round(v, 4) for v in tb],
+            "speedup_vs_alpha1": round(mixed_s / statistics.median(tb), 3),
             "iters": stb["iters"], "rel_resid": stb["rel_resid"],
             "y1_rel_diff_vs_alpha1": float(torch.linalg.vector_norm(yb - y) / torch.linalg.vector_norm(y))}
         ctx.set_alpha(args.alpha)
